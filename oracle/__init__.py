@@ -1,0 +1,8 @@
+"""CPU oracle for the Wilson-Dirac operator and CG on D^dagger D.
+
+TEST INFRASTRUCTURE ONLY: imported by the tests, the smoke check and the
+CPU-baseline leg of the benchmark, never by the library.  See ``wilson.py``.
+"""
+
+from .wilson import *  # noqa: F401,F403
+from .wilson import GAMMA, GAMMA5, ONE4  # noqa: F401
