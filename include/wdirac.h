@@ -1,0 +1,248 @@
+/*
+ * wdirac.h -- C ABI of the MI355X (gfx950) Wilson-Dirac library.
+ *
+ * The calls follow the paper's statement of the fermion problem (App. C,
+ * "Definition of Dirac operators"): build an operator from a gauge field and
+ * a hopping parameter kappa, apply D (``mul!(y,D,x)``), its adjoint (``D'``)
+ * or the normal operator D^dag D (``DdagD_operator``), and solve
+ * D^dag D x = b iteratively to a tolerance (``solve_DinvX!`` with
+ * ``eps_CG``).  Output arguments come first, as in the paper's mutating calls.
+ *
+ * Operator (the paper cites Wilson's formulation without printing it; the
+ * library fixes the textbook hopping-parameter form, r = 1):
+ *
+ *   (D psi)(x) = psi(x) - kappa * sum_mu [ (1 - g_mu) U_mu(x) s+ psi(x+mu)
+ *                                        + (1 + g_mu) U_mu(x-mu)^dag s- psi(x-mu) ]
+ *
+ * with the Euclidean chiral gamma basis g_k = [[0,-i sigma_k],[i sigma_k,0]],
+ * g_4 = [[0,1],[1,0]], g_5 = diag(1,1,-1,-1), and s+/s- = bc[mu] for a hop
+ * that crosses the lattice boundary in direction mu (else 1).
+ * Even-odd mode (WD_EO) works with the Schur complement on the even sites,
+ * D_hat = 1 - kappa^2 H_eo H_oe (D = 1 - kappa H); parity of a site is
+ * (x+y+z+t) mod 2.
+ *
+ * Data at the boundary (all device pointers, complex128 = two doubles re,im):
+ *   spinor field : [t][z][y][x][spin 4][colour 3]; colour fastest, matching
+ *                  the paper's element x[ic,ix,iy,iz,it,ialpha] (App. C,
+ *                  "Definition of pseudo-fermion fields").  nrhs fields are
+ *                  stored back to back: [rhs][t][z][y][x][4][3].
+ *   gauge field  : [mu = x,y,z,t][t][z][y][x][row 3][col 3] (the paper's
+ *                  U[mu], App. B).  Boundary signs are NOT folded in.
+ *   In WD_EO mode the odd sites of an input are ignored and the odd sites of
+ *   an output are written as zero.
+ *
+ * Memory ownership: the library never allocates device memory.  The caller
+ * allocates gauge stores and workspaces (size queries below) and keeps them
+ * alive while in use; the library keeps no pointer to x, y or b after a call
+ * returns.  A gauge store registered with wd_set_gauge must outlive every
+ * call that uses that precision on the lattice.
+ *
+ * Streams: ``stream`` is a hipStream_t (0 = the null stream).  apply calls
+ * are asynchronous on it; solve calls block the host until the solve ends.
+ *
+ * Errors: every call returns a wd_status; on error a thread-local message is
+ * available from wd_last_error().  Arguments are checked before any work is
+ * queued: on error nothing has been launched.
+ *
+ * Thread safety: calls on different lattices are independent; calls on one
+ * lattice must be serialised by the caller.
+ */
+#ifndef WDIRAC_H
+#define WDIRAC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t wd_status;
+enum {
+  WD_OK = 0,
+  WD_EINVAL = -1,         /* bad argument (shape, precision, null pointer, odd extent in EO) */
+  WD_EBUFSIZE = -2,       /* caller buffer smaller than the size query requires */
+  WD_ENOGAUGE = -3,       /* no gauge store of the requested precision registered */
+  WD_ENOTCONVERGED = -4,  /* maxiter reached; x holds the last iterate, stats are filled */
+  WD_ENONFINITE = -5,     /* NaN/Inf met in the source or during the iteration */
+  WD_EDEVICE = -6,        /* a HIP runtime call failed */
+  WD_EBUSY = -7,          /* server: request not admitted (no slot or memory) */
+  WD_ENOTFOUND = -8       /* server: unknown ticket */
+};
+
+typedef enum { WD_F64 = 0, WD_F32 = 1, WD_F16 = 2 } wd_prec;
+typedef enum { WD_FULL = 0, WD_EO = 1 } wd_precond;
+
+typedef struct wd_lattice_s* wd_lattice;
+
+/* Solver parameters (the paper's params dict: kappa, eps_CG, verbose). */
+typedef struct {
+  double tol;          /* stop when ||b - A x|| / ||b|| <= tol, true residual in FP64 */
+  int32_t maxiter;     /* iteration cap (inner iterations) */
+  int32_t inner;       /* wd_prec of the inner CG: F64 = plain FP64 CG, F32/F16 = mixed */
+  int32_t recon;       /* 18 or 12: link storage of the inner operator's gauge store */
+  double delta;        /* reliable update when ||r|| < delta * max ||r|| since the last one;
+                          0 = only at convergence (plain CG) */
+  int32_t precond;     /* wd_precond */
+  int32_t poll_every;  /* iterations between host convergence polls; 0 = automatic */
+  int32_t use_graph;   /* 1: replay captured hipGraphs of poll_every iterations */
+  int32_t timing;      /* 1: time every stencil launch with hipEvents (disables graphs) */
+} wd_solve_params;
+
+/* Per right-hand side result. */
+typedef struct {
+  int32_t status;            /* WD_OK, WD_ENOTCONVERGED or WD_ENONFINITE for this rhs */
+  int32_t iters;             /* inner CG iterations */
+  int32_t reliable_updates;  /* FP64 true-residual recomputations */
+  int32_t pad;
+  double true_resid;         /* last FP64 true relative residual */
+  double iter_resid;         /* last iterated relative residual */
+  double seconds;            /* wall time of the whole solve call */
+  double hop_ms;             /* with timing=1: summed duration of the stencil launches */
+  int64_t hop_launches;      /* with timing=1: number of stencil launches timed */
+  int64_t hop_site_updates;  /* stencil output sites x rhs processed by those launches */
+} wd_solve_stats;
+
+/* ---- lattice ---------------------------------------------------------- */
+
+/* L = {Lx, Ly, Lz, Lt}, each >= 2 and even (needed for the even-odd split and
+ * the checkerboard index); bc = per-direction boundary sign, +1 periodic or
+ * -1 antiperiodic.  Host-only; allocates a small host object. */
+wd_status wd_lattice_create(wd_lattice* out, const int32_t L[4], const int32_t bc[4]);
+wd_status wd_lattice_destroy(wd_lattice lat);
+
+/* Bytes of a gauge store of precision prec with recon = 18 (full 3x3) or 12
+ * (two rows; the third is rebuilt as the conjugate cross product of the first
+ * two, exact for SU(3)).  0 on bad arguments. */
+size_t wd_gauge_bytes(wd_lattice lat, int32_t prec, int32_t recon);
+
+/* Convert the complex128 gauge field U (device, boundary layout) into the
+ * caller-owned device store (wd_gauge_bytes bytes) and register it as the
+ * lattice's links of precision prec.  One store per precision; calling again
+ * replaces the registration.  Asynchronous on stream. */
+wd_status wd_set_gauge(wd_lattice lat, const void* U, void* store, size_t store_bytes,
+                       int32_t prec, int32_t recon, void* stream);
+
+/* ---- operator application -------------------------------------------- */
+
+/* Workspace bytes needed by wd_apply_D / wd_apply_DdagD at precision prec. */
+size_t wd_apply_workspace_bytes(wd_lattice lat, int32_t prec, int32_t nrhs);
+
+/* y = D x (dagger = 0) or y = D^dag x (dagger = 1) for nrhs fields; in WD_EO
+ * mode D_hat (resp. D_hat^dag) on the even sites.  The arithmetic runs in
+ * precision prec with that precision's registered gauge store; x and y stay
+ * complex128.  Asynchronous on stream. */
+wd_status wd_apply_D(wd_lattice lat, void* y, const void* x, int32_t nrhs, double kappa,
+                     int32_t dagger, int32_t precond, int32_t prec,
+                     void* ws, size_t ws_bytes, void* stream);
+
+/* y = D^dag D x (WD_FULL) or y = D_hat^dag D_hat x (WD_EO).  Asynchronous. */
+wd_status wd_apply_DdagD(wd_lattice lat, void* y, const void* x, int32_t nrhs, double kappa,
+                         int32_t precond, int32_t prec,
+                         void* ws, size_t ws_bytes, void* stream);
+
+/* ---- solver ------------------------------------------------------------ */
+
+/* Workspace bytes for wd_solve_DdagD with these parameters and nrhs fields. */
+size_t wd_solver_workspace_bytes(wd_lattice lat, const wd_solve_params* params, int32_t nrhs);
+
+/* Fill *params with defaults: tol 1e-10, maxiter 100000, inner F64, recon 18,
+ * delta 0, WD_EO, automatic polling, graphs on, timing off. */
+void wd_solve_params_default(wd_solve_params* params);
+
+/* Solve D^dag D x = b (WD_FULL) or D_hat^dag D_hat x_e = b_e (WD_EO) for nrhs
+ * right-hand sides at once; kappa[r] is the hopping parameter of rhs r.
+ * CG from x0 = 0; inner arithmetic in params->inner with FP64 reliable
+ * updates (x_h += x_l, r_h = b - A x_h recomputed with the FP64 store, FP64
+ * norms).  Needs the FP64 gauge store, and the inner precision's store when
+ * inner != F64.  stats has nrhs entries (host).  Blocks the host.  Returns
+ * WD_OK when every rhs converged, else the first failing rhs status. */
+wd_status wd_solve_DdagD(wd_lattice lat, void* x, const void* b, int32_t nrhs, const double* kappa,
+                         const wd_solve_params* params, void* ws, size_t ws_bytes,
+                         wd_solve_stats* stats, void* stream);
+
+/* ---- batched solve over several lattices in one launch sequence ------- */
+
+typedef struct {
+  wd_lattice lat;
+  void* x;              /* device, complex128 boundary layout, nrhs fields */
+  const void* b;        /* device, complex128 boundary layout, nrhs fields */
+  int32_t nrhs;         /* must be equal across the requests of one batch */
+  int32_t pad;
+  const double* kappa;  /* host, nrhs entries */
+} wd_solve_request;
+
+/* Workspace bytes for wd_solve_batch over these requests. */
+size_t wd_batch_workspace_bytes(int32_t nreq, const wd_solve_request* reqs, const wd_solve_params* params);
+
+/* Solve every request with one stencil launch per CG phase covering all of
+ * them (uneven lattices in one grid).  stats holds sum(nrhs) entries, in
+ * request order.  Blocks the host. */
+wd_status wd_solve_batch(int32_t nreq, const wd_solve_request* reqs, const wd_solve_params* params,
+                         void* ws, size_t ws_bytes, wd_solve_stats* stats, void* stream);
+
+/* ---- measurement and tuning ------------------------------------------ */
+
+/* Time n launches of the inner-iteration stencil (one even-odd hop, V/2 output
+ * sites x nrhs, precision prec) with hipEvents on stream; *ms_per_launch gets
+ * the mean duration.  Uses the tuned launch shape.  Needs
+ * wd_apply_workspace_bytes(lat, prec, nrhs) of workspace.  Blocks the host. */
+wd_status wd_time_hop(wd_lattice lat, int32_t prec, int32_t nrhs, int32_t n,
+                      void* ws, size_t ws_bytes, double* ms_per_launch, void* stream);
+
+/* Autotune the stencil launch shape (sites per workgroup, XCD-aware block
+ * order) for this lattice, precision and nrhs by timing every candidate on
+ * stream; the choice is kept in a process-wide table keyed by (dims, prec,
+ * recon, nrhs) and used by every later launch.  Needs
+ * wd_apply_workspace_bytes(lat, prec, nrhs).  Blocks the host.
+ * *best_sites_per_block / *best_swizzle receive the choice (may be NULL). */
+wd_status wd_autotune(wd_lattice lat, int32_t prec, int32_t nrhs, void* ws, size_t ws_bytes,
+                      int32_t* best_sites_per_block, int32_t* best_swizzle, void* stream);
+
+/* Read or write the tuning table as text ("Lx Ly Lz Lt prec recon nrhs sblk swz" lines).
+ * wd_tune_export returns the bytes needed (including the NUL) and writes at
+ * most cap bytes into buf (may be NULL). */
+size_t wd_tune_export(char* buf, size_t cap);
+wd_status wd_tune_import(const char* text);
+
+/* ---- serving ------------------------------------------------------------ */
+
+typedef struct wd_server_s* wd_server;
+
+/* A server owns a caller-provided device pool of pool_bytes and admits solve
+ * requests while their footprint (per-request workspace) fits in the pool and
+ * a slot (of max_slots) is free.  Admitted requests are solved together by a
+ * worker thread, one launch per CG phase over all running requests
+ * (continuous batching: requests join and leave at poll boundaries).  Gauge
+ * stores are the caller's (registered on each lattice) and stay resident. */
+wd_status wd_server_create(wd_server* out, void* pool, size_t pool_bytes, int32_t max_slots,
+                           const wd_solve_params* params, void* stream);
+wd_status wd_server_destroy(wd_server srv);
+
+/* Bytes of the pool a request of this lattice and nrhs would hold. */
+size_t wd_server_footprint(wd_server srv, wd_lattice lat, int32_t nrhs);
+
+/* Queue a solve of D^dag D x = b (nrhs fields, kappa[nrhs] host values
+ * copied at submit).  x and b are caller device buffers that must stay alive
+ * until the ticket completes.  Returns WD_EBUSY without queueing when the
+ * footprint can never fit the pool.  Requests wait FIFO for memory/slots. */
+wd_status wd_server_submit(wd_server srv, wd_lattice lat, void* x, const void* b, int32_t nrhs,
+                           const double* kappa, uint64_t* ticket);
+
+/* Non-blocking: returns 1 and fills stats[nrhs] (host) once the ticket has
+ * completed, 0 while it is queued or running, <0 on error. */
+int32_t wd_server_poll(wd_server srv, uint64_t ticket, wd_solve_stats* stats);
+
+/* Block until the ticket completes (timeout_ms < 0: no limit); 1 done, 0 timed out. */
+int32_t wd_server_wait(wd_server srv, uint64_t ticket, wd_solve_stats* stats, int32_t timeout_ms);
+
+/* ---- diagnostics --------------------------------------------------------- */
+const char* wd_status_string(wd_status s);
+const char* wd_last_error(void);
+const char* wd_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* WDIRAC_H */

@@ -1,0 +1,410 @@
+// CG engine: conjugate gradient on D^dag D (full lattice) or on the even-odd
+// Schur complement D_hat^dag D_hat, with the inner iteration in FP64, FP32 or
+// FP16 and FP64 reliable updates, for a set of solve items that may change
+// between poll blocks.
+//
+// One inner iteration (even-odd; FULL mode fuses the parities):
+//   t1 = H_oe p                               stencil, odd output
+//   t2 = p - c H_eo t1 ; alpha = rho/|t2|^2   stencil + reduction  (<p,A p> = |D_hat p|^2)
+//   t1 = H_oe g5 t2                           stencil
+//   r -= alpha (t2 - c g5 H_eo t1) ; |r|^2    stencil + reduction  (A p never stored)
+//   x += alpha p ; p = r + beta p             vector kernel
+// with c = kappa^2.  A reliable update (Sleijpen and van der Vorst; held rhs
+// only) does x_h += x, r_h = b - A x_h with the FP64 store, and resumes with
+// r = r_h, p = r + beta p.  All scalars stay on the device.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+
+#include "wd_host.h"
+
+namespace wd {
+
+int min_sblk(int nrhs) {
+  int s = 1;
+  while (s * nrhs < 32) s *= 2;
+  return s;
+}
+
+size_t states_bytes(size_t nstates) { return align_up(nstates * sizeof(RhsState)); }
+
+ItemLayout item_layout(const wd_lattice_s* lat, const wd_solve_params& p, int nrhs) {
+  ItemLayout l;
+  const size_t n = (size_t)lat->g.n;
+  const int np = p.precond == WD_EO ? 1 : 2;
+  const int P = p.inner, A = acc_prec(P);
+  const size_t vh = vec_bytes(F64, n, nrhs), va = vec_bytes(A, n, nrhs), vp = vec_bytes(P, n, nrhs);
+  size_t o = 0;
+  l.off_partial = o;
+  o += align_up((size_t)np * ((n + min_sblk(nrhs) - 1) / min_sblk(nrhs)) * nrhs * sizeof(double));
+  l.off_counter = o;
+  o += 256;
+  l.off_bh = o; o += np * vh;
+  l.off_xh = o; o += np * vh;
+  l.off_rh = o; o += np * vh;
+  l.off_h1 = o; o += np * vh;
+  l.off_h2 = o; o += np * vh;
+  l.off_x = o; o += np * va;
+  l.off_r = o; o += np * va;
+  l.off_p = o; o += np * vp;
+  l.off_t1 = o; o += np * vp;
+  l.off_t2 = o; o += np * vp;
+  l.hstride = vh;
+  l.astride = va;
+  l.vstride = vp;
+  l.total = o;
+  return l;
+}
+
+enum Role { R_NONE, R_P, R_T1, R_T2, R_BH, R_XH, R_H1, R_H2 };
+
+static void* role_ptr(const EItem* it, int role) {
+  const ItemLayout& l = it->lay;
+  char* b = it->base;
+  switch (role) {
+    case R_P: return b + l.off_p;
+    case R_T1: return b + l.off_t1;
+    case R_T2: return b + l.off_t2;
+    case R_BH: return b + l.off_bh;
+    case R_XH: return b + l.off_xh;
+    case R_H1: return b + l.off_h1;
+    case R_H2: return b + l.off_h2;
+  }
+  return nullptr;
+}
+
+struct Engine::Phase {
+  bool hop;
+  int prec;  // -1 = the inner precision
+  int mode;
+  int parity;
+  int g5in, g5out;
+  int mask, fin;
+  int in, out, aux;
+};
+
+wd_status Engine::run_phase(const std::vector<EItem*>& list, const Phase& ph0) {
+  Phase ph = ph0;
+  if (ph.prec < 0) ph.prec = p_.inner;
+  size_t i = 0;
+  while (i < list.size()) {
+    // a launch: consecutive items with the same nrhs, at most kMaxSlots
+    const int nrhs = list[i]->nrhs;
+    size_t j = i;
+    while (j < list.size() && j - i < (size_t)kMaxSlots && list[j]->nrhs == nrhs) ++j;
+    const wd_lattice_s* lat0 = list[i]->lat;
+    const int recon = lat0->store[ph.prec].recon;
+    const Tune t = tune_lookup(lat0, ph.prec, recon, nrhs);
+    Launch L = base_launch(nrhs, t, ph.parity);
+    L.g5in = ph.g5in;
+    L.g5out = ph.g5out;
+    L.mask = ph.mask;
+    L.fin = ph.fin;
+    L.nslots = (int)(j - i);
+    long long sites = 0;
+    for (size_t k = i; k < j; ++k) {
+      const EItem* it = list[k];
+      Slot& S = L.s[k - i];
+      fill_slot_geometry(S, it->lat, t.sblk, ph.parity);
+      S.gauge = (const char*)it->lat->store[ph.prec].ptr;
+      S.in = role_ptr(it, ph.in);
+      S.out = role_ptr(it, ph.out);
+      S.aux = role_ptr(it, ph.aux);
+      const ItemLayout& l = it->lay;
+      S.r = it->base + l.off_r;
+      S.x = it->base + l.off_x;
+      S.b = it->base + l.off_bh;
+      S.xh = it->base + l.off_xh;
+      S.rh = it->base + l.off_rh;
+      S.vstride = ph.prec == F64 ? l.hstride : l.vstride;
+      S.astride = l.astride;
+      S.hstride = l.hstride;
+      S.st = it->st;
+      S.partial = (double*)(it->base + l.off_partial);
+      S.counter = (unsigned*)(it->base + l.off_counter);
+      sites += (long long)it->lat->g.n * (ph.parity == 2 ? 2 : 1) * nrhs;
+    }
+    finish_launch(L);
+    if (ph.hop) {
+      hipError_t e = timer_ ? timer_->begin(stream_) : hipSuccess;
+      if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
+      e = launch_hop(L, ph.prec, recon, ph.mode, stream_);
+      if (e != hipSuccess) return hip_fail(e, "stencil launch");
+      e = timer_ ? timer_->end(stream_, sites) : hipSuccess;
+      if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
+    } else {
+      hipError_t e = launch_blas(L, ph.prec, ph.mode, stream_);
+      if (e != hipSuccess) return hip_fail(e, "vector kernel launch");
+    }
+    i = j;
+  }
+  return WD_OK;
+}
+
+wd_status Engine::run_iteration() {
+  static const Phase eo[5] = {
+      {true, -1, HOP_PLAIN, 1, 0, 0, MASK_RUN, FIN_NONE, R_P, R_T1, R_NONE},
+      {true, -1, HOP_XPAY, 0, 0, 0, MASK_RUN, FIN_ALPHA, R_T1, R_T2, R_P},
+      {true, -1, HOP_PLAIN, 1, 1, 0, MASK_ACTIVE, FIN_NONE, R_T2, R_T1, R_NONE},
+      {true, -1, HOP_CGR, 0, 0, 1, MASK_ACTIVE, FIN_CG, R_T1, R_NONE, R_T2},
+      {false, -1, BLAS_CGUPD, 0, 0, 0, MASK_ACTIVE, FIN_NONE, R_NONE, R_P, R_NONE},
+  };
+  static const Phase full[3] = {
+      {true, -1, HOP_XPAY, 2, 0, 0, MASK_RUN, FIN_ALPHA, R_P, R_T2, R_P},
+      {true, -1, HOP_CGR, 2, 1, 1, MASK_ACTIVE, FIN_CG, R_T2, R_NONE, R_T2},
+      {false, -1, BLAS_CGUPD, 2, 0, 0, MASK_ACTIVE, FIN_NONE, R_NONE, R_P, R_NONE},
+  };
+  const Phase* k = eo_ ? eo : full;
+  const int nk = eo_ ? 5 : 3;
+  for (int q = 0; q < nk; ++q) {
+    wd_status s = run_phase(items, k[q]);
+    if (s != WD_OK) return s;
+  }
+  return WD_OK;
+}
+
+wd_status Engine::run_reliable() {
+  static const Phase eo[6] = {
+      {false, -1, BLAS_RU_ACC, 0, 0, 0, MASK_HOLD, FIN_NONE, R_NONE, R_P, R_NONE},
+      {true, F64, HOP_PLAIN, 1, 0, 0, MASK_HOLD, FIN_NONE, R_XH, R_H1, R_NONE},
+      {true, F64, HOP_XPAY, 0, 0, 0, MASK_HOLD, FIN_NONE, R_H1, R_H2, R_XH},
+      {true, F64, HOP_PLAIN, 1, 1, 0, MASK_HOLD, FIN_NONE, R_H2, R_H1, R_NONE},
+      {true, F64, HOP_RESID, 0, 0, 1, MASK_HOLD, FIN_RESID, R_H1, R_NONE, R_H2},
+      {false, -1, BLAS_RU_FIN, 0, 0, 0, MASK_RU, FIN_NONE, R_NONE, R_P, R_NONE},
+  };
+  static const Phase full[4] = {
+      {false, -1, BLAS_RU_ACC, 2, 0, 0, MASK_HOLD, FIN_NONE, R_NONE, R_P, R_NONE},
+      {true, F64, HOP_XPAY, 2, 0, 0, MASK_HOLD, FIN_NONE, R_XH, R_H2, R_XH},
+      {true, F64, HOP_RESID, 2, 1, 1, MASK_HOLD, FIN_RESID, R_H2, R_NONE, R_H2},
+      {false, -1, BLAS_RU_FIN, 2, 0, 0, MASK_RU, FIN_NONE, R_NONE, R_P, R_NONE},
+  };
+  const Phase* k = eo_ ? eo : full;
+  const int nk = eo_ ? 6 : 4;
+  for (int q = 0; q < nk; ++q) {
+    wd_status s = run_phase(items, k[q]);
+    if (s != WD_OK) return s;
+  }
+  return WD_OK;
+}
+
+wd_status Engine::start_item(EItem* it) {
+  it->h_init.assign(it->nrhs, RhsState{});
+  for (int r = 0; r < it->nrhs; ++r) {
+    RhsState& s = it->h_init[r];
+    memset(&s, 0, sizeof s);
+    const double k = it->kappa[r];
+    s.stop2 = p_.tol * p_.tol;
+    s.delta2 = p_.delta * p_.delta;
+    s.c = eo_ ? k * k : k;
+    s.maxiter = p_.maxiter;
+    s.state = ST_RUN;
+  }
+  WD_HIP(hipMemcpyAsync(it->st, it->h_init.data(), it->nrhs * sizeof(RhsState), hipMemcpyHostToDevice, stream_));
+  WD_HIP(hipMemsetAsync(it->base + it->lay.off_counter, 0, 256, stream_));
+  WD_HIP(launch_spinor_import(it->b, it->base + it->lay.off_bh, it->lay.hstride, it->lat->g, it->nrhs, eo_ ? 1 : 2,
+                              F64, stream_));
+  const Phase init = {false, -1, BLAS_INIT, eo_ ? 0 : 2, 0, 0, MASK_NONE, FIN_INIT, R_NONE, R_P, R_NONE};
+  std::vector<EItem*> one{it};
+  it->started_block = blocks;
+  return run_phase(one, init);
+}
+
+wd_status Engine::export_item(EItem* it) {
+  WD_HIP(launch_spinor_export(it->base + it->lay.off_xh, it->lay.hstride, it->x, it->lat->g, it->nrhs, eo_ ? 1 : 2,
+                              F64, stream_));
+  return WD_OK;
+}
+
+void Engine::choose_block() {
+  long long work = 0;
+  for (auto* it : items) work += (long long)it->lat->g.n * it->nrhs * (eo_ ? 1 : 2);
+  int K = p_.poll_every;
+  if (K <= 0) K = (int)std::max(2LL, std::min(32LL, (1LL << 21) / std::max(1LL, work)));
+  int ru = p_.delta > 0.0 ? std::min(K, 4) : K;
+  if (K % ru) K = (K / ru + 1) * ru;
+  K_ = K;
+  ru_every_ = ru;
+}
+
+void Engine::drop_graph() {
+  if (gexec_) (void)hipGraphExecDestroy(gexec_);
+  if (graph_) (void)hipGraphDestroy(graph_);
+  gexec_ = nullptr;
+  graph_ = nullptr;
+}
+
+wd_status Engine::enqueue_direct() {
+  for (int j = 0; j < K_; ++j) {
+    wd_status s = run_iteration();
+    if (s != WD_OK) return s;
+    if ((j + 1) % ru_every_ == 0) {
+      s = run_reliable();
+      if (s != WD_OK) return s;
+    }
+  }
+  return WD_OK;
+}
+
+wd_status Engine::enqueue_block() {
+  if (items.empty()) return WD_OK;
+  const bool use_graph = p_.use_graph && !timer_;
+  if (!use_graph) {
+    choose_block();
+    ++blocks;
+    return enqueue_direct();
+  }
+  if (!gexec_) {
+    choose_block();
+    WD_HIP(hipStreamBeginCapture(stream_, hipStreamCaptureModeThreadLocal));
+    wd_status s = enqueue_direct();
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(stream_, &g);
+    if (s != WD_OK) {
+      if (g) (void)hipGraphDestroy(g);
+      return s;
+    }
+    if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+    graph_ = g;
+    e = hipGraphInstantiate(&gexec_, graph_, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+      drop_graph();
+      return hip_fail(e, "hipGraphInstantiate");
+    }
+  }
+  ++blocks;
+  WD_HIP(hipGraphLaunch(gexec_, stream_));
+  return WD_OK;
+}
+
+wd_status stats_from_state(const RhsState& s, double seconds, const HopTimer* t, wd_solve_stats& o) {
+  memset(&o, 0, sizeof o);
+  o.iters = s.iters;
+  o.reliable_updates = s.reliable;
+  const double bn = s.bnorm2 > 0.0 ? s.bnorm2 : 1.0;
+  o.true_resid = std::sqrt(s.true_res2 / bn);
+  o.iter_resid = std::sqrt(s.iter_res2 / bn);
+  o.seconds = seconds;
+  if (t && t->on) {
+    o.hop_launches = (long long)(t->used / 2);
+    o.hop_site_updates = t->site_updates;
+  }
+  if (s.state == ST_DONE) o.status = WD_OK;
+  else if (s.state == ST_NONFINITE) o.status = WD_ENONFINITE;
+  else o.status = WD_ENOTCONVERGED;
+  return o.status;
+}
+
+static bool finished(int st) { return st == ST_DONE || st == ST_NOTCONV || st == ST_NONFINITE; }
+
+// The legacy null stream cannot be captured into a graph.  Solves given it run
+// on a per-thread blocking stream instead, which the null stream orders with
+// the caller's other work (legacy default-stream semantics).
+static hipStream_t solve_stream(hipStream_t s, wd_status* st) {
+  *st = WD_OK;
+  if (s) return s;
+  static thread_local hipStream_t own = nullptr;
+  if (!own) {
+    hipError_t e = hipStreamCreate(&own);
+    if (e != hipSuccess) {
+      *st = hip_fail(e, "hipStreamCreate");
+      own = nullptr;
+      return nullptr;
+    }
+  }
+  return own;
+}
+
+wd_status run_batch(std::vector<EItem>& items, const wd_solve_params& p, RhsState* states, hipStream_t stream_in,
+                    wd_solve_stats* stats) {
+  auto t0 = std::chrono::steady_clock::now();
+  wd_status sst;
+  hipStream_t stream = solve_stream(stream_in, &sst);
+  if (sst != WD_OK) return sst;
+  HopTimer timer;
+  timer.on = p.timing != 0;
+  Engine eng(p, stream, states, timer.on ? &timer : nullptr);
+  size_t nst = 0;
+  for (auto& it : items) nst += (size_t)it.nrhs;
+  wd_status result = WD_OK;
+  for (auto& it : items) {
+    eng.items.push_back(&it);
+    if ((result = eng.start_item(&it)) != WD_OK) return result;
+  }
+  RhsState* hs[2] = {nullptr, nullptr};
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  do {
+    hipError_t e;
+    if ((e = hipHostMalloc((void**)&hs[0], nst * sizeof(RhsState), hipHostMallocDefault)) != hipSuccess ||
+        (e = hipHostMalloc((void**)&hs[1], nst * sizeof(RhsState), hipHostMallocDefault)) != hipSuccess ||
+        (e = hipEventCreateWithFlags(&ev[0], hipEventDisableTiming)) != hipSuccess ||
+        (e = hipEventCreateWithFlags(&ev[1], hipEventDisableTiming)) != hipSuccess) {
+      result = hip_fail(e, "poll buffers");
+      break;
+    }
+    // Two blocks in flight: while the GPU runs block k+1 the host reads the
+    // states copied after block k.  Finished rhs make later kernels no-ops.
+    auto post = [&](int k) -> wd_status {
+      wd_status s = eng.enqueue_block();
+      if (s != WD_OK) return s;
+      hipError_t e2 = hipMemcpyAsync(hs[k], states, nst * sizeof(RhsState), hipMemcpyDeviceToHost, stream);
+      if (e2 != hipSuccess) return hip_fail(e2, "state copy");
+      e2 = hipEventRecord(ev[k], stream);
+      if (e2 != hipSuccess) return hip_fail(e2, "hipEventRecord");
+      return WD_OK;
+    };
+    if ((result = post(0)) != WD_OK) break;
+    const long long block_cap = (long long)p.maxiter / 2 + 64;
+    int cur = 0;
+    for (;;) {
+      if ((result = post(1 - cur)) != WD_OK) break;
+      e = hipEventSynchronize(ev[cur]);
+      if (e != hipSuccess) {
+        result = hip_fail(e, "hipEventSynchronize");
+        break;
+      }
+      bool all = true;
+      for (size_t q = 0; q < nst; ++q) all = all && finished(hs[cur][q].state);
+      if (all) break;
+      if (eng.blocks > block_cap) break;  // the device caps iterations; this only bounds the host loop
+      cur = 1 - cur;
+    }
+  } while (false);
+  hipError_t es = hipStreamSynchronize(stream);
+  if (result == WD_OK && es != hipSuccess) result = hip_fail(es, "hipStreamSynchronize");
+  std::vector<RhsState> fin(nst);
+  if (result == WD_OK) {
+    hipError_t e = hipMemcpy(fin.data(), states, nst * sizeof(RhsState), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) result = hip_fail(e, "final state copy");
+  }
+  if (result == WD_OK) {
+    for (auto& it : items)
+      if ((result = eng.export_item(&it)) != WD_OK) break;
+    hipError_t e = hipStreamSynchronize(stream);
+    if (result == WD_OK && e != hipSuccess) result = hip_fail(e, "hipStreamSynchronize");
+  }
+  for (int k = 0; k < 2; ++k) {
+    if (hs[k]) (void)hipHostFree(hs[k]);
+    if (ev[k]) (void)hipEventDestroy(ev[k]);
+  }
+  const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  if (result != WD_OK) {
+    timer.release();
+    return result;
+  }
+  const double hop_ms = timer.on ? timer.total_ms() : 0.0;
+  wd_status worst = WD_OK;
+  for (size_t q = 0; q < nst; ++q) {
+    wd_status st = stats_from_state(fin[q], secs, &timer, stats[q]);
+    stats[q].hop_ms = hop_ms;
+    if (worst == WD_OK && st != WD_OK) worst = st;
+  }
+  timer.release();
+  if (worst == WD_ENONFINITE) set_error("non-finite value met in the solve");
+  if (worst == WD_ENOTCONVERGED) set_error("solve did not reach the tolerance within maxiter");
+  return worst;
+}
+
+}  // namespace wd

@@ -1,0 +1,117 @@
+// The Wilson hopping stencil with fused epilogues.
+//
+// One thread computes (H in)(x) for one output site x and one rhs: for each
+// of the 8 directions it loads the neighbour spinor, spin-projects it to a
+// half spinor (adds and i-swaps only), multiplies the half spinor by the
+// link (U or U^dag), applies the boundary sign, and accumulates the rebuilt
+// full spinor: 8 x (12 + 132) + 7 x 24 = 1320 flop per output site.
+// The epilogue then forms one of
+//   HOP_PLAIN : out = [g5] H [g5] in
+//   HOP_XPAY  : out = aux - c [g5] H [g5] in          (+ ||out||^2, FIN_ALPHA)
+//   HOP_CGR   : r  -= alpha (aux - c [g5] H [g5] in)  (+ ||r||^2,  FIN_CG)
+//   HOP_RESID : rh  = b - (aux - c [g5] H [g5] in)    (+ ||rh||^2, FIN_RESID)
+// so that the CG on D_hat^dag D_hat never stores A p separately and its dot
+// products ride on the stencil's own output.
+#include "wd_kcommon.h"
+#include "wd_kernels.h"
+
+namespace wd {
+
+template <int P> struct AccOf { static constexpr int value = P == F16 ? F32 : P; };
+
+template <int P, int R, int MODE>
+__global__ void __launch_bounds__(kBlock) hop_kernel(const Launch L) {
+  using T = typename RealOf<P>::T;
+  constexpr int A = AccOf<P>::value;
+  using TA = typename RealOf<A>::T;
+  const Tile t = make_tile(L);
+  const Slot& S = L.s[t.slot];
+  // Launches with a reduction always run every block: the finalize step must
+  // see every rhs, also the ones this launch leaves untouched.
+  if (L.fin == FIN_NONE && !slot_selected(L, S)) return;
+  const bool both = L.parity == 2;
+  const int par = t.parity;
+  const size_t ne = (size_t)S.g.n * L.nrhs;
+  const size_t e = (size_t)t.site * L.nrhs + t.rhs;
+  double v = 0.0;
+  if (t.valid && rhs_selected(S.st, L.mask, t.rhs)) {
+    const char* in = (const char*)S.in + (both ? (size_t)(1 - par) * S.vstride : 0);
+    spinor<T> acc;
+    hop_site<P, R>(S.g, par, t.site, t.rhs, L.nrhs, S.gauge, in, S.bc, L.g5in != 0, acc);
+    if (L.g5out) gamma5_inplace(acc);
+    if (MODE == HOP_PLAIN) {
+      char* out = (char*)S.out + (both ? (size_t)par * S.vstride : 0);
+      SpinorFmt<P>::store(out, ne, e, acc);
+    } else {
+      const T c = (T)(S.st ? S.st[t.rhs].c : L.coef);
+      const char* aux = (const char*)S.aux + (both ? (size_t)par * S.vstride : 0);
+      spinor<T> a;
+      SpinorFmt<P>::load(aux, ne, e, a);
+#pragma unroll
+      for (int k = 0; k < 12; ++k) {
+        a.c[k].re -= c * acc.c[k].re;
+        a.c[k].im -= c * acc.c[k].im;
+      }
+      if (MODE == HOP_XPAY) {
+        char* out = (char*)S.out + (both ? (size_t)par * S.vstride : 0);
+        SpinorFmt<P>::store(out, ne, e, a);
+        v = spinor_norm2(a);
+      } else if (MODE == HOP_CGR) {
+        const TA alpha = (TA)S.st[t.rhs].alpha;
+        char* r = (char*)S.r + (both ? (size_t)par * S.astride : 0);
+        spinor<TA> rv;
+        SpinorFmt<A>::load(r, ne, e, rv);
+#pragma unroll
+        for (int k = 0; k < 12; ++k) {
+          rv.c[k].re -= alpha * (TA)a.c[k].re;
+          rv.c[k].im -= alpha * (TA)a.c[k].im;
+        }
+        SpinorFmt<A>::store(r, ne, e, rv);
+        v = spinor_norm2(rv);
+      } else {  // HOP_RESID, FP64 only
+        const char* b = (const char*)S.b + (both ? (size_t)par * S.hstride : 0);
+        char* rh = (char*)S.rh + (both ? (size_t)par * S.hstride : 0);
+        spinor<double> bv, res;
+        SpinorFmt<F64>::load(b, ne, e, bv);
+#pragma unroll
+        for (int k = 0; k < 12; ++k) {
+          res.c[k].re = bv.c[k].re - (double)a.c[k].re;
+          res.c[k].im = bv.c[k].im - (double)a.c[k].im;
+        }
+        SpinorFmt<F64>::store(rh, ne, e, res);
+        v = spinor_norm2(res);
+      }
+    }
+  }
+  if (L.fin != FIN_NONE) reduce_and_finalize(L, S, t, v);
+}
+
+template <int P, int R, int MODE>
+static hipError_t launch_one(const Launch& L, hipStream_t stream) {
+  dim3 grid((unsigned)L.total_blocks), block((unsigned)(L.sblk * L.nrhs));
+  hipLaunchKernelGGL((hop_kernel<P, R, MODE>), grid, block, 0, stream, L);
+  return hipGetLastError();
+}
+
+template <int P, int R>
+static hipError_t launch_mode(const Launch& L, int mode, hipStream_t stream) {
+  switch (mode) {
+    case HOP_PLAIN: return launch_one<P, R, HOP_PLAIN>(L, stream);
+    case HOP_XPAY: return launch_one<P, R, HOP_XPAY>(L, stream);
+    case HOP_CGR: return launch_one<P, R, HOP_CGR>(L, stream);
+    case HOP_RESID:
+      if constexpr (P == F64) return launch_one<P, R, HOP_RESID>(L, stream);
+      return hipErrorInvalidValue;
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_hop(const Launch& L, int prec, int recon, int mode, hipStream_t stream) {
+  if (L.total_blocks <= 0) return hipSuccess;
+  if (prec == F64) return recon == 12 ? launch_mode<F64, 12>(L, mode, stream) : launch_mode<F64, 18>(L, mode, stream);
+  if (prec == F32) return recon == 12 ? launch_mode<F32, 12>(L, mode, stream) : launch_mode<F32, 18>(L, mode, stream);
+  if (prec == F16) return recon == 12 ? launch_mode<F16, 12>(L, mode, stream) : launch_mode<F16, 18>(L, mode, stream);
+  return hipErrorInvalidValue;
+}
+
+}  // namespace wd

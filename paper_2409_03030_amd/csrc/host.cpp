@@ -1,0 +1,571 @@
+// Host driver and C ABI of the Wilson-Dirac library.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <sstream>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "wd_host.h"
+
+namespace wd {
+
+// ---------------------------------------------------------------------------
+// errors
+// ---------------------------------------------------------------------------
+static thread_local std::string g_last_error;
+
+void set_error(const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+}
+
+wd_status fail(wd_status s, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return s;
+}
+
+wd_status hip_fail(hipError_t e, const char* what) {
+  return fail(WD_EDEVICE, "%s failed: %s", what, hipGetErrorString(e));
+}
+
+// ---------------------------------------------------------------------------
+// sizes
+// ---------------------------------------------------------------------------
+size_t vec_bytes(int prec, size_t n, int nrhs) {
+  const size_t ne = n * (size_t)nrhs;
+  switch (prec) {
+    case F64: return align_up(SpinorFmt<F64>::bytes(ne));
+    case F32: return align_up(SpinorFmt<F32>::bytes(ne));
+    case F16: return align_up(SpinorFmt<F16>::bytes(ne));
+  }
+  return 0;
+}
+
+size_t gauge_bytes(const Geom& g, int prec, int recon) {
+  const size_t n = (size_t)g.n;
+  size_t dir = 0;
+  if (recon != 18 && recon != 12) return 0;
+  if (prec == F64) dir = recon == 18 ? link_dir_bytes<F64, 18>(n) : link_dir_bytes<F64, 12>(n);
+  else if (prec == F32) dir = recon == 18 ? link_dir_bytes<F32, 18>(n) : link_dir_bytes<F32, 12>(n);
+  else if (prec == F16) dir = recon == 18 ? link_dir_bytes<F16, 18>(n) : link_dir_bytes<F16, 12>(n);
+  else return 0;
+  return 8 * dir;
+}
+
+// ---------------------------------------------------------------------------
+// tuning table
+// ---------------------------------------------------------------------------
+using TuneKey = std::tuple<int, int, int, int, int, int, int>;
+static std::mutex g_tune_mu;
+static std::map<TuneKey, Tune> g_tune;
+
+static TuneKey tkey(const wd_lattice_s* lat, int prec, int recon, int nrhs) {
+  return TuneKey(lat->L[0], lat->L[1], lat->L[2], lat->L[3], prec, recon, nrhs);
+}
+
+int default_sblk(int nrhs) {
+  int s = 1;
+  while (s * 2 * nrhs <= kBlock) s *= 2;
+  if (nrhs == 1) s = 128;
+  return s;
+}
+
+static bool valid_sblk(int sblk, int nrhs) {
+  return sblk >= 1 && (sblk & (sblk - 1)) == 0 && sblk * nrhs <= kBlock && sblk * nrhs >= 32;
+}
+
+Tune tune_lookup(const wd_lattice_s* lat, int prec, int recon, int nrhs) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  auto it = g_tune.find(tkey(lat, prec, recon, nrhs));
+  if (it != g_tune.end()) return it->second;
+  return Tune{default_sblk(nrhs), 1};
+}
+
+void tune_store(const wd_lattice_s* lat, int prec, int recon, int nrhs, Tune t) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tune[tkey(lat, prec, recon, nrhs)] = t;
+}
+
+// ---------------------------------------------------------------------------
+// launch assembly
+// ---------------------------------------------------------------------------
+void fill_slot_geometry(Slot& S, const wd_lattice_s* lat, int sblk, int parity) {
+  S.g = lat->g;
+  for (int mu = 0; mu < 4; ++mu) S.bc[mu] = (float)lat->bc[mu];
+  const int nbp = (lat->g.n + sblk - 1) / sblk;
+  S.nblk = parity == 2 ? 2 * nbp : nbp;
+}
+
+void finish_launch(Launch& L) {
+  int b = 0;
+  for (int i = 0; i < L.nslots; ++i) {
+    L.s[i].blk0 = b;
+    b += L.s[i].nblk;
+  }
+  L.total_blocks = b;
+}
+
+Launch base_launch(int nrhs, const Tune& t, int parity) {
+  Launch L;
+  memset(&L, 0, sizeof L);
+  L.nrhs = nrhs;
+  L.sblk = t.sblk;
+  L.swz = t.swz;
+  L.parity = parity;
+  return L;
+}
+
+// ---------------------------------------------------------------------------
+// timing
+// ---------------------------------------------------------------------------
+hipError_t HopTimer::begin(hipStream_t s) {
+  if (!on) return hipSuccess;
+  if (used + 2 > ev.size()) {
+    for (int i = 0; i < 256; ++i) {
+      hipEvent_t e;
+      hipError_t r = hipEventCreate(&e);
+      if (r != hipSuccess) return r;
+      ev.push_back(e);
+    }
+  }
+  return hipEventRecord(ev[used], s);
+}
+
+hipError_t HopTimer::end(hipStream_t s, long long sites) {
+  if (!on) return hipSuccess;
+  hipError_t r = hipEventRecord(ev[used + 1], s);
+  used += 2;
+  site_updates += sites;
+  return r;
+}
+
+double HopTimer::total_ms() {
+  double t = 0.0;
+  for (size_t i = 0; i + 1 < used; i += 2) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, ev[i], ev[i + 1]) == hipSuccess) t += ms;
+  }
+  return t;
+}
+
+void HopTimer::release() {
+  for (auto e : ev) (void)hipEventDestroy(e);
+  ev.clear();
+  used = 0;
+}
+
+// ---------------------------------------------------------------------------
+// argument checks
+// ---------------------------------------------------------------------------
+wd_status check_params(const wd_solve_params& p) {
+  if (!(p.tol > 0.0) || !std::isfinite(p.tol)) return fail(WD_EINVAL, "tol must be positive and finite");
+  if (p.maxiter <= 0) return fail(WD_EINVAL, "maxiter must be positive");
+  if (p.inner < F64 || p.inner > F16) return fail(WD_EINVAL, "inner precision %d unknown", p.inner);
+  if (p.recon != 0 && p.recon != 12 && p.recon != 18) return fail(WD_EINVAL, "recon must be 0, 12 or 18");
+  if (!(p.delta >= 0.0 && p.delta < 1.0)) return fail(WD_EINVAL, "delta must be in [0, 1)");
+  if (p.precond != WD_FULL && p.precond != WD_EO) return fail(WD_EINVAL, "precond %d unknown", p.precond);
+  if (p.poll_every < 0 || p.poll_every > 4096) return fail(WD_EINVAL, "poll_every out of range");
+  return WD_OK;
+}
+
+wd_status check_lattice_for(const wd_lattice_s* lat, int prec, int precond) {
+  if (!lat) return fail(WD_EINVAL, "null lattice");
+  if (prec < F64 || prec > F16) return fail(WD_EINVAL, "precision %d unknown", prec);
+  if (precond != WD_FULL && precond != WD_EO) return fail(WD_EINVAL, "precond %d unknown", precond);
+  if (!lat->store[prec].ptr) return fail(WD_ENOGAUGE, "no gauge store of precision %d registered", prec);
+  return WD_OK;
+}
+
+}  // namespace wd
+
+using namespace wd;
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+const char* wd_version(void) { return "wdirac 0.1 (gfx950)"; }
+
+const char* wd_last_error(void) { return g_last_error.c_str(); }
+
+const char* wd_status_string(wd_status s) {
+  switch (s) {
+    case WD_OK: return "ok";
+    case WD_EINVAL: return "invalid argument";
+    case WD_EBUFSIZE: return "buffer too small";
+    case WD_ENOGAUGE: return "no gauge field of that precision";
+    case WD_ENOTCONVERGED: return "not converged";
+    case WD_ENONFINITE: return "non-finite value";
+    case WD_EDEVICE: return "device error";
+    case WD_EBUSY: return "busy";
+    case WD_ENOTFOUND: return "not found";
+  }
+  return "unknown status";
+}
+
+wd_status wd_lattice_create(wd_lattice* out, const int32_t L[4], const int32_t bc[4]) {
+  if (!out || !L || !bc) return fail(WD_EINVAL, "null argument");
+  *out = nullptr;
+  long long V = 1;
+  for (int mu = 0; mu < 4; ++mu) {
+    if (L[mu] < 2 || (L[mu] & 1)) return fail(WD_EINVAL, "extent L[%d] = %d must be even and >= 2", mu, L[mu]);
+    if (bc[mu] != 1 && bc[mu] != -1) return fail(WD_EINVAL, "bc[%d] = %d must be +1 or -1", mu, bc[mu]);
+    V *= L[mu];
+  }
+  if (V > (1LL << 30)) return fail(WD_EINVAL, "lattice volume %lld too large", V);
+  wd_lattice_s* lat = new wd_lattice_s();
+  for (int mu = 0; mu < 4; ++mu) {
+    lat->L[mu] = L[mu];
+    lat->bc[mu] = bc[mu];
+    lat->g.L[mu] = L[mu];
+  }
+  lat->g.hx = L[0] / 2;
+  lat->g.n = (int)(V / 2);
+  *out = lat;
+  return WD_OK;
+}
+
+wd_status wd_lattice_destroy(wd_lattice lat) {
+  delete lat;
+  return WD_OK;
+}
+
+size_t wd_gauge_bytes(wd_lattice lat, int32_t prec, int32_t recon) {
+  if (!lat) return 0;
+  return gauge_bytes(lat->g, prec, recon);
+}
+
+wd_status wd_set_gauge(wd_lattice lat, const void* U, void* store, size_t store_bytes, int32_t prec, int32_t recon,
+                       void* stream) {
+  if (!lat || !U || !store) return fail(WD_EINVAL, "null argument");
+  if (prec < F64 || prec > F16) return fail(WD_EINVAL, "precision %d unknown", prec);
+  if (recon != 18 && recon != 12) return fail(WD_EINVAL, "recon must be 18 or 12");
+  const size_t need = gauge_bytes(lat->g, prec, recon);
+  if (store_bytes < need) return fail(WD_EBUFSIZE, "gauge store holds %zu bytes, %zu needed", store_bytes, need);
+  WD_HIP(launch_gauge_import(U, store, lat->g, prec, recon, (hipStream_t)stream));
+  lat->store[prec].ptr = store;
+  lat->store[prec].recon = recon;
+  return WD_OK;
+}
+
+size_t wd_apply_workspace_bytes(wd_lattice lat, int32_t prec, int32_t nrhs) {
+  if (!lat || prec < F64 || prec > F16 || nrhs < 1) return 0;
+  return 4 * 2 * vec_bytes(prec, (size_t)lat->g.n, nrhs);
+}
+
+static wd_status apply_common(wd_lattice lat, void* y, const void* x, int32_t nrhs, double kappa, int32_t precond,
+                              int32_t prec, void* ws, size_t ws_bytes, void* stream, bool normal, int dagger) {
+  wd_status s = check_lattice_for(lat, prec, precond);
+  if (s != WD_OK) return s;
+  if (!y || !x || !ws) return fail(WD_EINVAL, "null argument");
+  if (nrhs < 1 || nrhs > kBlock / 2) return fail(WD_EINVAL, "nrhs = %d out of range [1, %d]", nrhs, kBlock / 2);
+  if (!std::isfinite(kappa)) return fail(WD_EINVAL, "kappa not finite");
+  const size_t need = wd_apply_workspace_bytes(lat, prec, nrhs);
+  if (ws_bytes < need) return fail(WD_EBUFSIZE, "workspace holds %zu bytes, %zu needed", ws_bytes, need);
+  hipStream_t st = (hipStream_t)stream;
+  const size_t vb = vec_bytes(prec, (size_t)lat->g.n, nrhs);
+  char* w = (char*)ws;
+  char* vin = w;
+  char* vt = w + 2 * vb;
+  char* vout = w + 4 * vb;
+  char* vout2 = w + 6 * vb;
+  const int recon = lat->store[prec].recon;
+  const Tune t = tune_lookup(lat, prec, recon, nrhs);
+  const bool eo = precond == WD_EO;
+  auto hop = [&](int mode, int parity, const void* in, void* out, const void* aux, double coef, int g5in,
+                 int g5out) -> wd_status {
+    Launch L = base_launch(nrhs, t, parity);
+    L.nslots = 1;
+    L.g5in = g5in;
+    L.g5out = g5out;
+    L.mask = MASK_NONE;
+    L.fin = FIN_NONE;
+    L.coef = coef;
+    Slot& S = L.s[0];
+    fill_slot_geometry(S, lat, t.sblk, parity);
+    S.gauge = (const char*)lat->store[prec].ptr;
+    S.in = in;
+    S.out = out;
+    S.aux = aux;
+    S.vstride = vb;
+    finish_launch(L);
+    WD_HIP(launch_hop(L, prec, recon, mode, st));
+    return WD_OK;
+  };
+  WD_HIP(launch_spinor_import(x, vin, vb, lat->g, nrhs, eo ? 1 : 2, prec, st));
+  // first operator: D (or D^dag)
+  const int d1 = normal ? 0 : dagger;
+  if (eo) {
+    if ((s = hop(HOP_PLAIN, 1, vin, vt, nullptr, 0.0, d1, 0)) != WD_OK) return s;
+    if ((s = hop(HOP_XPAY, 0, vt, vout, vin, kappa * kappa, 0, d1)) != WD_OK) return s;
+  } else {
+    if ((s = hop(HOP_XPAY, 2, vin, vout, vin, kappa, d1, d1)) != WD_OK) return s;
+  }
+  char* res = vout;
+  if (normal) {  // then D^dag = g5 D g5
+    if (eo) {
+      if ((s = hop(HOP_PLAIN, 1, vout, vt, nullptr, 0.0, 1, 0)) != WD_OK) return s;
+      if ((s = hop(HOP_XPAY, 0, vt, vout2, vout, kappa * kappa, 0, 1)) != WD_OK) return s;
+    } else {
+      if ((s = hop(HOP_XPAY, 2, vout, vout2, vout, kappa, 1, 1)) != WD_OK) return s;
+    }
+    res = vout2;
+  }
+  WD_HIP(launch_spinor_export(res, vb, y, lat->g, nrhs, eo ? 1 : 2, prec, st));
+  return WD_OK;
+}
+
+wd_status wd_apply_D(wd_lattice lat, void* y, const void* x, int32_t nrhs, double kappa, int32_t dagger,
+                     int32_t precond, int32_t prec, void* ws, size_t ws_bytes, void* stream) {
+  if (dagger != 0 && dagger != 1) return fail(WD_EINVAL, "dagger must be 0 or 1");
+  return apply_common(lat, y, x, nrhs, kappa, precond, prec, ws, ws_bytes, stream, false, dagger);
+}
+
+wd_status wd_apply_DdagD(wd_lattice lat, void* y, const void* x, int32_t nrhs, double kappa, int32_t precond,
+                         int32_t prec, void* ws, size_t ws_bytes, void* stream) {
+  return apply_common(lat, y, x, nrhs, kappa, precond, prec, ws, ws_bytes, stream, true, 0);
+}
+
+void wd_solve_params_default(wd_solve_params* p) {
+  if (!p) return;
+  memset(p, 0, sizeof *p);
+  p->tol = 1e-10;
+  p->maxiter = 100000;
+  p->inner = WD_F64;
+  p->recon = 0;
+  p->delta = 0.0;
+  p->precond = WD_EO;
+  p->poll_every = 0;
+  p->use_graph = 1;
+  p->timing = 0;
+}
+
+static wd_status check_item(wd_lattice lat, const wd_solve_params& p) {
+  if (!lat) return fail(WD_EINVAL, "null lattice");
+  if (!lat->store[F64].ptr) return fail(WD_ENOGAUGE, "the FP64 gauge store is needed for the true residual");
+  if (!lat->store[p.inner].ptr) return fail(WD_ENOGAUGE, "no gauge store of the inner precision %d", p.inner);
+  if (p.recon != 0 && lat->store[p.inner].recon != p.recon)
+    return fail(WD_ENOGAUGE, "inner gauge store has recon %d, %d requested", lat->store[p.inner].recon, p.recon);
+  return WD_OK;
+}
+
+size_t wd_solver_workspace_bytes(wd_lattice lat, const wd_solve_params* params, int32_t nrhs) {
+  if (!lat || !params || nrhs < 1) return 0;
+  return states_bytes((size_t)nrhs) + item_layout(lat, *params, nrhs).total;
+}
+
+size_t wd_batch_workspace_bytes(int32_t nreq, const wd_solve_request* reqs, const wd_solve_params* params) {
+  if (nreq < 1 || !reqs || !params) return 0;
+  size_t nst = 0, tot = 0;
+  for (int i = 0; i < nreq; ++i) {
+    if (!reqs[i].lat || reqs[i].nrhs < 1) return 0;
+    nst += (size_t)reqs[i].nrhs;
+    tot += item_layout(reqs[i].lat, *params, reqs[i].nrhs).total;
+  }
+  return states_bytes(nst) + tot;
+}
+
+wd_status wd_solve_batch(int32_t nreq, const wd_solve_request* reqs, const wd_solve_params* params, void* ws,
+                         size_t ws_bytes, wd_solve_stats* stats, void* stream) {
+  if (nreq < 1 || !reqs || !params || !ws || !stats) return fail(WD_EINVAL, "null argument or empty batch");
+  wd_status s = check_params(*params);
+  if (s != WD_OK) return s;
+  for (int i = 0; i < nreq; ++i) {
+    const int nrhs = reqs[i].nrhs;
+    if (nrhs < 1 || nrhs > kBlock / 2) return fail(WD_EINVAL, "request %d: nrhs = %d out of range [1, %d]", i, nrhs, kBlock / 2);
+    if (!reqs[i].x || !reqs[i].b || !reqs[i].kappa) return fail(WD_EINVAL, "request %d has a null pointer", i);
+    if ((s = check_item(reqs[i].lat, *params)) != WD_OK) return s;
+    for (int r = 0; r < nrhs; ++r)
+      if (!std::isfinite(reqs[i].kappa[r])) return fail(WD_EINVAL, "request %d: kappa[%d] not finite", i, r);
+  }
+  const size_t need = wd_batch_workspace_bytes(nreq, reqs, params);
+  if (ws_bytes < need) return fail(WD_EBUFSIZE, "workspace holds %zu bytes, %zu needed", ws_bytes, need);
+  size_t nst = 0;
+  for (int i = 0; i < nreq; ++i) nst += (size_t)reqs[i].nrhs;
+  char* w = (char*)ws;
+  RhsState* states = (RhsState*)w;
+  size_t off = states_bytes(nst);
+  int si = 0;
+  std::vector<EItem> items((size_t)nreq);
+  for (int i = 0; i < nreq; ++i) {
+    EItem& it = items[i];
+    it.lat = reqs[i].lat;
+    it.x = reqs[i].x;
+    it.b = reqs[i].b;
+    it.nrhs = reqs[i].nrhs;
+    it.kappa.assign(reqs[i].kappa, reqs[i].kappa + it.nrhs);
+    it.lay = item_layout(it.lat, *params, it.nrhs);
+    it.base = w + off;
+    off += it.lay.total;
+    it.st = states + si;
+    it.state_index = si;
+    si += it.nrhs;
+  }
+  return run_batch(items, *params, states, (hipStream_t)stream, stats);
+}
+
+wd_status wd_solve_DdagD(wd_lattice lat, void* x, const void* b, int32_t nrhs, const double* kappa,
+                         const wd_solve_params* params, void* ws, size_t ws_bytes, wd_solve_stats* stats,
+                         void* stream) {
+  wd_solve_request r;
+  memset(&r, 0, sizeof r);
+  r.lat = lat;
+  r.x = x;
+  r.b = b;
+  r.nrhs = nrhs;
+  r.kappa = kappa;
+  if (!lat) return fail(WD_EINVAL, "null lattice");
+  return wd_solve_batch(1, &r, params, ws, ws_bytes, stats, stream);
+}
+
+// ---------------------------------------------------------------------------
+// measurement and tuning
+// ---------------------------------------------------------------------------
+static wd_status time_hop_shape(wd_lattice lat, int prec, int nrhs, int n, const Tune& t, char* ws, double* ms,
+                                hipStream_t st) {
+  const size_t vb = vec_bytes(prec, (size_t)lat->g.n, nrhs);
+  const int recon = lat->store[prec].recon;
+  Launch L = base_launch(nrhs, t, 1);
+  L.nslots = 1;
+  Slot& S = L.s[0];
+  fill_slot_geometry(S, lat, t.sblk, 1);
+  S.gauge = (const char*)lat->store[prec].ptr;
+  S.in = ws;
+  S.out = ws + 2 * vb;
+  S.vstride = vb;
+  finish_launch(L);
+  hipEvent_t e0, e1;
+  WD_HIP(hipEventCreate(&e0));
+  WD_HIP(hipEventCreate(&e1));
+  wd_status res = WD_OK;
+  hipError_t e = hipSuccess;
+  for (int i = 0; i < 3 && e == hipSuccess; ++i) e = launch_hop(L, prec, recon, HOP_PLAIN, st);
+  if (e == hipSuccess) e = hipEventRecord(e0, st);
+  for (int i = 0; i < n && e == hipSuccess; ++i) e = launch_hop(L, prec, recon, HOP_PLAIN, st);
+  if (e == hipSuccess) e = hipEventRecord(e1, st);
+  if (e == hipSuccess) e = hipEventSynchronize(e1);
+  float f = 0.f;
+  if (e == hipSuccess) e = hipEventElapsedTime(&f, e0, e1);
+  if (e != hipSuccess) res = hip_fail(e, "timed stencil launches");
+  else *ms = (double)f / n;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return res;
+}
+
+wd_status wd_time_hop(wd_lattice lat, int32_t prec, int32_t nrhs, int32_t n, void* ws, size_t ws_bytes,
+                      double* ms_per_launch, void* stream) {
+  wd_status s = check_lattice_for(lat, prec, WD_EO);
+  if (s != WD_OK) return s;
+  if (!ws || !ms_per_launch || n < 1) return fail(WD_EINVAL, "bad argument");
+  if (nrhs < 1 || nrhs > kBlock / 2) return fail(WD_EINVAL, "nrhs out of range");
+  if (ws_bytes < wd_apply_workspace_bytes(lat, prec, nrhs)) return fail(WD_EBUFSIZE, "workspace too small");
+  const Tune t = tune_lookup(lat, prec, lat->store[prec].recon, nrhs);
+  return time_hop_shape(lat, prec, nrhs, n, t, (char*)ws, ms_per_launch, (hipStream_t)stream);
+}
+
+wd_status wd_autotune(wd_lattice lat, int32_t prec, int32_t nrhs, void* ws, size_t ws_bytes,
+                      int32_t* best_sites_per_block, int32_t* best_swizzle, void* stream) {
+  wd_status s = check_lattice_for(lat, prec, WD_EO);
+  if (s != WD_OK) return s;
+  if (!ws) return fail(WD_EINVAL, "null workspace");
+  if (nrhs < 1 || nrhs > kBlock / 2) return fail(WD_EINVAL, "nrhs out of range");
+  if (ws_bytes < wd_apply_workspace_bytes(lat, prec, nrhs)) return fail(WD_EBUFSIZE, "workspace too small");
+  hipStream_t st = (hipStream_t)stream;
+  const size_t vb = vec_bytes(prec, (size_t)lat->g.n, nrhs);
+  char* w = (char*)ws;
+  // a deterministic input: the workspace's input block filled with a pattern
+  std::vector<unsigned char> pat(vb);
+  for (size_t i = 0; i < vb; ++i) pat[i] = (unsigned char)((i * 2654435761u) >> 13) & 0x3f;
+  WD_HIP(hipMemcpyAsync(w, pat.data(), vb, hipMemcpyHostToDevice, st));
+  WD_HIP(hipStreamSynchronize(st));
+  const int recon = lat->store[prec].recon;
+  std::vector<unsigned char> ref, got;
+  double best = 1e30;
+  Tune bt{default_sblk(nrhs), 1};
+  for (int sblk = 1; sblk <= kBlock; sblk *= 2) {
+    if (!valid_sblk(sblk, nrhs)) continue;
+    for (int swz = 0; swz <= 1; ++swz) {
+      Tune t{sblk, swz};
+      WD_HIP(hipMemsetAsync(w + 2 * vb, 0, vb, st));
+      double ms = 0.0;
+      if ((s = time_hop_shape(lat, prec, nrhs, 20, t, w, &ms, st)) != WD_OK) return s;
+      // every shape must produce the same bytes: the per-site arithmetic does not depend on tiling
+      got.resize(vb);
+      WD_HIP(hipMemcpy(got.data(), w + 2 * vb, vb, hipMemcpyDeviceToHost));
+      if (ref.empty()) ref = got;
+      else if (memcmp(ref.data(), got.data(), vb) != 0)
+        return fail(WD_EDEVICE, "tuning candidate sblk=%d swz=%d changed the stencil output", sblk, swz);
+      if (ms < best) {
+        best = ms;
+        bt = t;
+      }
+    }
+  }
+  (void)recon;
+  tune_store(lat, prec, lat->store[prec].recon, nrhs, bt);
+  if (best_sites_per_block) *best_sites_per_block = bt.sblk;
+  if (best_swizzle) *best_swizzle = bt.swz;
+  return WD_OK;
+}
+
+size_t wd_tune_export(char* buf, size_t cap) {
+  std::ostringstream os;
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    for (auto& kv : g_tune) {
+      const TuneKey& k = kv.first;
+      os << std::get<0>(k) << ' ' << std::get<1>(k) << ' ' << std::get<2>(k) << ' ' << std::get<3>(k) << ' '
+         << std::get<4>(k) << ' ' << std::get<5>(k) << ' ' << std::get<6>(k) << ' ' << kv.second.sblk << ' '
+         << kv.second.swz << '\n';
+    }
+  }
+  const std::string s = os.str();
+  if (buf && cap > 0) {
+    const size_t m = std::min(cap - 1, s.size());
+    memcpy(buf, s.data(), m);
+    buf[m] = 0;
+  }
+  return s.size() + 1;
+}
+
+wd_status wd_tune_import(const char* text) {
+  if (!text) return fail(WD_EINVAL, "null text");
+  std::istringstream is(text);
+  std::string line;
+  std::vector<std::pair<TuneKey, Tune>> rows;
+  while (std::getline(is, line)) {
+    if (line.empty()) continue;
+    std::istringstream ls(line);
+    int v[9];
+    for (int i = 0; i < 9; ++i)
+      if (!(ls >> v[i])) return fail(WD_EINVAL, "malformed tuning line '%s'", line.c_str());
+    if (!valid_sblk(v[7], v[6]) || (v[8] != 0 && v[8] != 1))
+      return fail(WD_EINVAL, "invalid tuning values in '%s'", line.c_str());
+    rows.push_back({TuneKey(v[0], v[1], v[2], v[3], v[4], v[5], v[6]), Tune{v[7], v[8]}});
+  }
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  for (auto& r : rows) g_tune[r.first] = r.second;
+  return WD_OK;
+}
+
+}  // extern "C"

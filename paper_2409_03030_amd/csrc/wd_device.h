@@ -1,0 +1,469 @@
+// Device-side building blocks of the Wilson-Dirac stencil: storage formats,
+// checkerboard geometry, spin projection and SU(3) products.
+//
+// Every function here is __host__ __device__ so that the per-site arithmetic
+// can also be driven from a plain CPU loop when checking indexing.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_fp16.h>
+#include <stdint.h>
+
+#define WD_HD __host__ __device__ __forceinline__
+
+namespace wd {
+
+enum Prec : int { F64 = 0, F32 = 1, F16 = 2 };
+
+template <int P> struct RealOf { using T = float; };
+template <> struct RealOf<F64> { using T = double; };
+
+template <typename T> struct cplx { T re, im; };
+
+template <typename T> WD_HD cplx<T> cmul(cplx<T> a, cplx<T> b) {
+  return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+// conj(a) * b
+template <typename T> WD_HD cplx<T> cjmul(cplx<T> a, cplx<T> b) {
+  return {a.re * b.re + a.im * b.im, a.re * b.im - a.im * b.re};
+}
+template <typename T> WD_HD cplx<T> cadd(cplx<T> a, cplx<T> b) { return {a.re + b.re, a.im + b.im}; }
+template <typename T> WD_HD cplx<T> csub(cplx<T> a, cplx<T> b) { return {a.re - b.re, a.im - b.im}; }
+// a + i b, a - i b
+template <typename T> WD_HD cplx<T> cadd_i(cplx<T> a, cplx<T> b) { return {a.re - b.im, a.im + b.re}; }
+template <typename T> WD_HD cplx<T> csub_i(cplx<T> a, cplx<T> b) { return {a.re + b.im, a.im - b.re}; }
+template <typename T> WD_HD cplx<T> cneg(cplx<T> a) { return {-a.re, -a.im}; }
+template <typename T> WD_HD cplx<T> ctimes_i(cplx<T> a) { return {-a.im, a.re}; }     // i a
+template <typename T> WD_HD cplx<T> ctimes_mi(cplx<T> a) { return {a.im, -a.re}; }    // -i a
+template <typename T> WD_HD cplx<T> cconj(cplx<T> a) { return {a.re, -a.im}; }
+template <typename T> WD_HD cplx<T> cscale(cplx<T> a, T s) { return {a.re * s, a.im * s}; }
+
+// A full spinor: 4 spins x 3 colours; component k = 3*spin + colour.
+template <typename T> struct spinor { cplx<T> c[12]; };
+// A half spinor after spin projection: 2 spins x 3 colours.
+template <typename T> struct half_spinor { cplx<T> c[6]; };
+template <typename T> struct su3 { cplx<T> e[9]; };  // row-major e[3*row + col]
+
+// ---------------------------------------------------------------------------
+// Spinor vectors.  One parity block of nrhs fields over n sites is stored as
+// [chunk][site][rhs] of 16-byte chunks (consecutive lanes -> consecutive
+// (site, rhs) -> coalesced 16-byte accesses):
+//   F64: 12 chunks of double2 (one complex each)
+//   F32:  6 chunks of float4  (two complexes each)
+//   F16:  3 chunks of 8 halves (four complexes each), followed by one float
+//         scale per (site, rhs): stored value = component / scale, where the
+//         scale is the largest |real or imaginary part| of the site's 24 reals.
+// ---------------------------------------------------------------------------
+template <int P> struct SpinorFmt;
+
+template <> struct SpinorFmt<F64> {
+  static constexpr int chunks = 12;
+  WD_HD static size_t bytes(size_t ne) { return ne * 12 * 16; }
+  WD_HD static void load(const void* base, size_t ne, size_t e, spinor<double>& s) {
+    const double2* v = (const double2*)base;
+#pragma unroll
+    for (int k = 0; k < 12; ++k) {
+      double2 d = v[k * ne + e];
+      s.c[k] = {d.x, d.y};
+    }
+  }
+  WD_HD static void store(void* base, size_t ne, size_t e, const spinor<double>& s) {
+    double2* v = (double2*)base;
+#pragma unroll
+    for (int k = 0; k < 12; ++k) v[k * ne + e] = make_double2(s.c[k].re, s.c[k].im);
+  }
+};
+
+template <> struct SpinorFmt<F32> {
+  static constexpr int chunks = 6;
+  WD_HD static size_t bytes(size_t ne) { return ne * 6 * 16; }
+  WD_HD static void load(const void* base, size_t ne, size_t e, spinor<float>& s) {
+    const float4* v = (const float4*)base;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+      float4 d = v[k * ne + e];
+      s.c[2 * k] = {d.x, d.y};
+      s.c[2 * k + 1] = {d.z, d.w};
+    }
+  }
+  WD_HD static void store(void* base, size_t ne, size_t e, const spinor<float>& s) {
+    float4* v = (float4*)base;
+#pragma unroll
+    for (int k = 0; k < 6; ++k)
+      v[k * ne + e] = make_float4(s.c[2 * k].re, s.c[2 * k].im, s.c[2 * k + 1].re, s.c[2 * k + 1].im);
+  }
+};
+
+union h8 {
+  uint4 u;
+  __half2 h[4];
+};
+
+template <> struct SpinorFmt<F16> {
+  static constexpr int chunks = 3;
+  WD_HD static size_t data_bytes(size_t ne) { return ne * 3 * 16; }
+  WD_HD static size_t bytes(size_t ne) { return data_bytes(ne) + ne * 4; }
+  WD_HD static void load(const void* base, size_t ne, size_t e, spinor<float>& s) {
+    const uint4* v = (const uint4*)base;
+    const float* sc = (const float*)((const char*)base + data_bytes(ne));
+    float a = sc[e];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      h8 d;
+      d.u = v[k * ne + e];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        float2 f = __half22float2(d.h[j]);
+        s.c[4 * k + j] = {f.x * a, f.y * a};
+      }
+    }
+  }
+  WD_HD static void store(void* base, size_t ne, size_t e, const spinor<float>& s) {
+    uint4* v = (uint4*)base;
+    float* sc = (float*)((char*)base + data_bytes(ne));
+    float m = 0.f;
+#pragma unroll
+    for (int k = 0; k < 12; ++k) m = fmaxf(m, fmaxf(fabsf(s.c[k].re), fabsf(s.c[k].im)));
+    float inv = m > 0.f ? 1.0f / m : 0.f;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      h8 d;
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        d.h[j] = __floats2half2_rn(s.c[4 * k + j].re * inv, s.c[4 * k + j].im * inv);
+      v[k * ne + e] = d.u;
+    }
+    sc[e] = m;
+  }
+};
+
+// ---------------------------------------------------------------------------
+// Links.  One store holds [parity][mu][chunk][site] for the links rooted at
+// each site (U_mu(x) lives with site x), n sites per parity.
+//   recon 18: all nine complexes; recon 12: rows 0 and 1, the third row is
+//   rebuilt as conj(row0 x row1), exact for SU(3).
+//   F64: double2 per complex.  F32-18: float2 per complex; F32-12: float4 per
+//   complex pair.  F16-18: half2 per complex; F16-12: 4 halves per pair.
+// ---------------------------------------------------------------------------
+template <int P, int R> struct LinkFmt;
+
+template <typename T> WD_HD void reconstruct_row2(su3<T>& u) {
+  // row2 = conj(row0 x row1)
+  u.e[6] = cconj(csub(cmul(u.e[1], u.e[5]), cmul(u.e[2], u.e[4])));
+  u.e[7] = cconj(csub(cmul(u.e[2], u.e[3]), cmul(u.e[0], u.e[5])));
+  u.e[8] = cconj(csub(cmul(u.e[0], u.e[4]), cmul(u.e[1], u.e[3])));
+}
+
+template <int R> struct LinkFmt<F64, R> {
+  static constexpr int ncplx = R == 18 ? 9 : 6;
+  static constexpr int chunk_bytes = 16;
+  static constexpr int chunks = ncplx;
+  WD_HD static void load(const void* base, size_t n, size_t s, su3<double>& u) {
+    const double2* v = (const double2*)base;
+#pragma unroll
+    for (int k = 0; k < ncplx; ++k) {
+      double2 d = v[k * n + s];
+      u.e[k] = {d.x, d.y};
+    }
+    if (R == 12) reconstruct_row2(u);
+  }
+  WD_HD static void store(void* base, size_t n, size_t s, const su3<double>& u) {
+    double2* v = (double2*)base;
+#pragma unroll
+    for (int k = 0; k < ncplx; ++k) v[k * n + s] = make_double2(u.e[k].re, u.e[k].im);
+  }
+};
+
+template <> struct LinkFmt<F32, 18> {
+  static constexpr int chunks = 9;
+  static constexpr int chunk_bytes = 8;
+  WD_HD static void load(const void* base, size_t n, size_t s, su3<float>& u) {
+    const float2* v = (const float2*)base;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+      float2 d = v[k * n + s];
+      u.e[k] = {d.x, d.y};
+    }
+  }
+  WD_HD static void store(void* base, size_t n, size_t s, const su3<float>& u) {
+    float2* v = (float2*)base;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) v[k * n + s] = make_float2(u.e[k].re, u.e[k].im);
+  }
+};
+
+template <> struct LinkFmt<F32, 12> {
+  static constexpr int chunks = 3;
+  static constexpr int chunk_bytes = 16;
+  WD_HD static void load(const void* base, size_t n, size_t s, su3<float>& u) {
+    const float4* v = (const float4*)base;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      float4 d = v[k * n + s];
+      u.e[2 * k] = {d.x, d.y};
+      u.e[2 * k + 1] = {d.z, d.w};
+    }
+    reconstruct_row2(u);
+  }
+  WD_HD static void store(void* base, size_t n, size_t s, const su3<float>& u) {
+    float4* v = (float4*)base;
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+      v[k * n + s] = make_float4(u.e[2 * k].re, u.e[2 * k].im, u.e[2 * k + 1].re, u.e[2 * k + 1].im);
+  }
+};
+
+template <> struct LinkFmt<F16, 18> {
+  static constexpr int chunks = 9;
+  static constexpr int chunk_bytes = 4;
+  WD_HD static void load(const void* base, size_t n, size_t s, su3<float>& u) {
+    const __half2* v = (const __half2*)base;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+      float2 d = __half22float2(v[k * n + s]);
+      u.e[k] = {d.x, d.y};
+    }
+  }
+  WD_HD static void store(void* base, size_t n, size_t s, const su3<float>& u) {
+    __half2* v = (__half2*)base;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) v[k * n + s] = __floats2half2_rn(u.e[k].re, u.e[k].im);
+  }
+};
+
+union h4 {
+  uint2 u;
+  __half2 h[2];
+};
+
+template <> struct LinkFmt<F16, 12> {
+  static constexpr int chunks = 3;
+  static constexpr int chunk_bytes = 8;
+  WD_HD static void load(const void* base, size_t n, size_t s, su3<float>& u) {
+    const uint2* v = (const uint2*)base;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      h4 d;
+      d.u = v[k * n + s];
+      float2 a = __half22float2(d.h[0]);
+      float2 b = __half22float2(d.h[1]);
+      u.e[2 * k] = {a.x, a.y};
+      u.e[2 * k + 1] = {b.x, b.y};
+    }
+    reconstruct_row2(u);
+  }
+  WD_HD static void store(void* base, size_t n, size_t s, const su3<float>& u) {
+    uint2* v = (uint2*)base;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      h4 d;
+      d.h[0] = __floats2half2_rn(u.e[2 * k].re, u.e[2 * k].im);
+      d.h[1] = __floats2half2_rn(u.e[2 * k + 1].re, u.e[2 * k + 1].im);
+      v[k * n + s] = d.u;
+    }
+  }
+};
+
+template <int P, int R> WD_HD size_t link_dir_bytes(size_t n) {
+  return (size_t)LinkFmt<P, R>::chunks * LinkFmt<P, R>::chunk_bytes * n;
+}
+
+// ---------------------------------------------------------------------------
+// Checkerboard geometry.  Lexicographic index i = x + Lx (y + Ly (z + Lz t));
+// the checkerboard index of a site within its parity is i / 2 (Lx even).
+// ---------------------------------------------------------------------------
+struct Geom {
+  int L[4];   // Lx, Ly, Lz, Lt
+  int hx;     // Lx / 2
+  int n;      // sites per parity
+};
+
+struct Coord {
+  int c[4];
+  int rest;   // y + Ly (z + Lz t): the cb index is x/2 + hx * rest
+};
+
+WD_HD Coord site_coord(const Geom& g, int parity, int s) {
+  Coord k;
+  int xh = s % g.hx;
+  int rest = s / g.hx;
+  int y = rest % g.L[1];
+  int r2 = rest / g.L[1];
+  int z = r2 % g.L[2];
+  int t = r2 / g.L[2];
+  k.c[0] = 2 * xh + ((parity + y + z + t) & 1);
+  k.c[1] = y;
+  k.c[2] = z;
+  k.c[3] = t;
+  k.rest = rest;
+  return k;
+}
+
+// cb index of the neighbour x + dir*mu_hat (dir = +1 or -1), with wrap.
+WD_HD int neighbour_cb(const Geom& g, const Coord& k, int mu, int dir) {
+  int c = k.c[mu] + dir;
+  if (c == g.L[mu]) c = 0;
+  if (c < 0) c = g.L[mu] - 1;
+  int x = mu == 0 ? c : k.c[0];
+  int y = mu == 1 ? c : k.c[1];
+  int z = mu == 2 ? c : k.c[2];
+  int t = mu == 3 ? c : k.c[3];
+  return (x >> 1) + g.hx * (y + g.L[1] * (z + g.L[2] * t));
+}
+
+// ---------------------------------------------------------------------------
+// Spin projection in the chiral basis.  For the forward hop the projector is
+// (1 - g_mu), for the backward hop (1 + g_mu).  Writing g_mu = [[0, A],[A^dag, 0]]
+// with A_k = -i sigma_k, A_4 = 1, the projected spinor is fixed by its upper
+// two spins h = psi_up -/+ A psi_low; its lower two spins are -/+ A^dag h.
+// The colour product commutes with the spin projection, so only h is
+// multiplied by the link and the lower spins are rebuilt afterwards.
+// ---------------------------------------------------------------------------
+template <int MU, int DIR, typename T>
+WD_HD void project(const spinor<T>& p, half_spinor<T>& h) {
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    cplx<T> s0 = p.c[a], s1 = p.c[3 + a], s2 = p.c[6 + a], s3 = p.c[9 + a];
+    if (DIR > 0) {  // 1 - g_mu
+      if (MU == 0) { h.c[a] = cadd_i(s0, s3); h.c[3 + a] = cadd_i(s1, s2); }
+      if (MU == 1) { h.c[a] = cadd(s0, s3);   h.c[3 + a] = csub(s1, s2); }
+      if (MU == 2) { h.c[a] = cadd_i(s0, s2); h.c[3 + a] = csub_i(s1, s3); }
+      if (MU == 3) { h.c[a] = csub(s0, s2);   h.c[3 + a] = csub(s1, s3); }
+    } else {        // 1 + g_mu
+      if (MU == 0) { h.c[a] = csub_i(s0, s3); h.c[3 + a] = csub_i(s1, s2); }
+      if (MU == 1) { h.c[a] = csub(s0, s3);   h.c[3 + a] = cadd(s1, s2); }
+      if (MU == 2) { h.c[a] = csub_i(s0, s2); h.c[3 + a] = cadd_i(s1, s3); }
+      if (MU == 3) { h.c[a] = cadd(s0, s2);   h.c[3 + a] = cadd(s1, s3); }
+    }
+  }
+}
+
+// acc += full spinor rebuilt from the link-multiplied half spinor g.
+template <int MU, int DIR, typename T>
+WD_HD void accumulate(spinor<T>& acc, const half_spinor<T>& g) {
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    cplx<T> g0 = g.c[a], g1 = g.c[3 + a];
+    acc.c[a] = cadd(acc.c[a], g0);
+    acc.c[3 + a] = cadd(acc.c[3 + a], g1);
+    cplx<T> l2, l3;
+    if (DIR > 0) {  // lower = -A^dag g
+      if (MU == 0) { l2 = ctimes_mi(g1); l3 = ctimes_mi(g0); }
+      if (MU == 1) { l2 = cneg(g1);      l3 = g0; }
+      if (MU == 2) { l2 = ctimes_mi(g0); l3 = ctimes_i(g1); }
+      if (MU == 3) { l2 = cneg(g0);      l3 = cneg(g1); }
+    } else {        // lower = +A^dag g
+      if (MU == 0) { l2 = ctimes_i(g1);  l3 = ctimes_i(g0); }
+      if (MU == 1) { l2 = g1;            l3 = cneg(g0); }
+      if (MU == 2) { l2 = ctimes_i(g0);  l3 = ctimes_mi(g1); }
+      if (MU == 3) { l2 = g0;            l3 = g1; }
+    }
+    acc.c[6 + a] = cadd(acc.c[6 + a], l2);
+    acc.c[9 + a] = cadd(acc.c[9 + a], l3);
+  }
+}
+
+// g = U h  (colour matrix on both spins)
+template <typename T>
+WD_HD void mul_link(const su3<T>& u, const half_spinor<T>& h, half_spinor<T>& g) {
+#pragma unroll
+  for (int sp = 0; sp < 2; ++sp) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      cplx<T> s = cmul(u.e[3 * a], h.c[3 * sp]);
+      s = cadd(s, cmul(u.e[3 * a + 1], h.c[3 * sp + 1]));
+      s = cadd(s, cmul(u.e[3 * a + 2], h.c[3 * sp + 2]));
+      g.c[3 * sp + a] = s;
+    }
+  }
+}
+
+// g = U^dag h
+template <typename T>
+WD_HD void mul_link_dag(const su3<T>& u, const half_spinor<T>& h, half_spinor<T>& g) {
+#pragma unroll
+  for (int sp = 0; sp < 2; ++sp) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      cplx<T> s = cjmul(u.e[a], h.c[3 * sp]);
+      s = cadd(s, cjmul(u.e[3 + a], h.c[3 * sp + 1]));
+      s = cadd(s, cjmul(u.e[6 + a], h.c[3 * sp + 2]));
+      g.c[3 * sp + a] = s;
+    }
+  }
+}
+
+template <typename T> WD_HD void gamma5_inplace(spinor<T>& s) {
+#pragma unroll
+  for (int k = 6; k < 12; ++k) s.c[k] = cneg(s.c[k]);
+}
+
+template <typename T> WD_HD void spinor_zero(spinor<T>& s) {
+#pragma unroll
+  for (int k = 0; k < 12; ++k) s.c[k] = {T(0), T(0)};
+}
+
+template <typename T> WD_HD double spinor_norm2(const spinor<T>& s) {
+  double acc = 0.0;
+#pragma unroll
+  for (int k = 0; k < 12; ++k) acc += (double)s.c[k].re * (double)s.c[k].re + (double)s.c[k].im * (double)s.c[k].im;
+  return acc;
+}
+
+template <typename TO, typename TI> WD_HD void spinor_convert(spinor<TO>& o, const spinor<TI>& i) {
+#pragma unroll
+  for (int k = 0; k < 12; ++k) o.c[k] = {(TO)i.c[k].re, (TO)i.c[k].im};
+}
+
+// ---------------------------------------------------------------------------
+// The hopping term at one output site: acc = H in (optionally gamma5 on in).
+// gauge points at the start of the store; in points at the input parity
+// block.  ne = n * nrhs is the chunk stride of the spinor block.
+// ---------------------------------------------------------------------------
+template <int P, int R, int MU, int DIR>
+WD_HD void hop_dir(const Geom& g, const Coord& k, int parity, int s, int rhs, int nrhs,
+                   const char* gauge, const void* in, float bc_sign, bool g5in,
+                   spinor<typename RealOf<P>::T>& acc) {
+  using T = typename RealOf<P>::T;
+  const size_t n = (size_t)g.n;
+  const size_t ne = n * (size_t)nrhs;
+  int nb = neighbour_cb(g, k, MU, DIR);
+  spinor<T> p;
+  SpinorFmt<P>::load(in, ne, (size_t)nb * nrhs + rhs, p);
+  if (g5in) gamma5_inplace(p);
+  half_spinor<T> h, gh;
+  project<MU, DIR>(p, h);
+  bool crosses = DIR > 0 ? (k.c[MU] == g.L[MU] - 1) : (k.c[MU] == 0);
+  if (crosses && bc_sign < 0.f) {
+#pragma unroll
+    for (int j = 0; j < 6; ++j) h.c[j] = cneg(h.c[j]);
+  }
+  su3<T> u;
+  // forward: U_mu(x), rooted at the output site (parity `parity`);
+  // backward: U_mu(x - mu), rooted at the neighbour (other parity).
+  const int lp = DIR > 0 ? parity : 1 - parity;
+  const size_t ls = DIR > 0 ? (size_t)s : (size_t)nb;
+  const char* lbase = gauge + (size_t)(lp * 4 + MU) * link_dir_bytes<P, R>(n);
+  LinkFmt<P, R>::load(lbase, n, ls, u);
+  if (DIR > 0) mul_link(u, h, gh);
+  else mul_link_dag(u, h, gh);
+  accumulate<MU, DIR>(acc, gh);
+}
+
+template <int P, int R>
+WD_HD void hop_site(const Geom& g, int parity, int s, int rhs, int nrhs, const char* gauge,
+                    const void* in, const float bc[4], bool g5in,
+                    spinor<typename RealOf<P>::T>& acc) {
+  Coord k = site_coord(g, parity, s);
+  spinor_zero(acc);
+  hop_dir<P, R, 0, +1>(g, k, parity, s, rhs, nrhs, gauge, in, bc[0], g5in, acc);
+  hop_dir<P, R, 0, -1>(g, k, parity, s, rhs, nrhs, gauge, in, bc[0], g5in, acc);
+  hop_dir<P, R, 1, +1>(g, k, parity, s, rhs, nrhs, gauge, in, bc[1], g5in, acc);
+  hop_dir<P, R, 1, -1>(g, k, parity, s, rhs, nrhs, gauge, in, bc[1], g5in, acc);
+  hop_dir<P, R, 2, +1>(g, k, parity, s, rhs, nrhs, gauge, in, bc[2], g5in, acc);
+  hop_dir<P, R, 2, -1>(g, k, parity, s, rhs, nrhs, gauge, in, bc[2], g5in, acc);
+  hop_dir<P, R, 3, +1>(g, k, parity, s, rhs, nrhs, gauge, in, bc[3], g5in, acc);
+  hop_dir<P, R, 3, -1>(g, k, parity, s, rhs, nrhs, gauge, in, bc[3], g5in, acc);
+}
+
+}  // namespace wd

@@ -1,0 +1,149 @@
+// Host-side internals: lattice object, error reporting, tuning table and
+// the batched CG driver shared by the C ABI and the server.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/wdirac.h"
+#include "wd_kernels.h"
+
+struct wd_lattice_s {
+  wd::Geom g;
+  int32_t L[4];
+  int32_t bc[4];
+  struct Store {
+    void* ptr = nullptr;
+    int recon = 0;
+  } store[3];
+};
+
+namespace wd {
+
+void set_error(const char* fmt, ...);
+wd_status fail(wd_status s, const char* fmt, ...);
+wd_status hip_fail(hipError_t e, const char* what);
+
+#define WD_HIP(call)                                  \
+  do {                                                \
+    hipError_t _e = (call);                           \
+    if (_e != hipSuccess) return hip_fail(_e, #call); \
+  } while (0)
+
+inline size_t align_up(size_t v, size_t a = 256) { return (v + a - 1) / a * a; }
+
+// Bytes of one parity block of nrhs spinors over n sites at precision prec.
+size_t vec_bytes(int prec, size_t n, int nrhs);
+size_t gauge_bytes(const Geom& g, int prec, int recon);
+inline int acc_prec(int prec) { return prec == F16 ? F32 : prec; }
+
+struct Tune {
+  int sblk;  // sites per block (power of two, sblk * nrhs <= kBlock)
+  int swz;   // XCD-aware block order
+};
+Tune tune_lookup(const wd_lattice_s* lat, int prec, int recon, int nrhs);
+void tune_store(const wd_lattice_s* lat, int prec, int recon, int nrhs, Tune t);
+int default_sblk(int nrhs);
+
+// Slot of a launch for a lattice; blocks for `parity` (0/1 or 2 = both).
+void fill_slot_geometry(Slot& S, const wd_lattice_s* lat, int sblk, int parity);
+void finish_launch(Launch& L);
+Launch base_launch(int nrhs, const Tune& t, int parity);
+int min_sblk(int nrhs);  // smallest block size the partial buffers allow
+
+// Events around stencil launches (timing mode).
+struct HopTimer {
+  bool on = false;
+  std::vector<hipEvent_t> ev;
+  size_t used = 0;
+  long long site_updates = 0;
+  hipError_t begin(hipStream_t s);
+  hipError_t end(hipStream_t s, long long sites);
+  double total_ms();
+  void release();
+};
+
+// Workspace of one solve item (a lattice with nrhs fields), relative to the
+// item's base.  The per-rhs states live in a separate array shared by every
+// item of an engine so that one copy polls all of them.
+struct ItemLayout {
+  size_t off_partial, off_counter;
+  size_t off_bh, off_xh, off_rh, off_h1, off_h2;  // FP64 vectors
+  size_t off_x, off_r;                            // accumulation precision
+  size_t off_p, off_t1, off_t2;                   // inner precision
+  size_t hstride, astride, vstride;               // parity strides (FULL mode)
+  size_t total;
+};
+ItemLayout item_layout(const wd_lattice_s* lat, const wd_solve_params& p, int nrhs);
+size_t states_bytes(size_t nstates);
+
+// One solve in an engine.
+struct EItem {
+  wd_lattice_s* lat = nullptr;
+  void* x = nullptr;
+  const void* b = nullptr;
+  std::vector<double> kappa;
+  int nrhs = 1;
+  ItemLayout lay{};
+  char* base = nullptr;             // device workspace of the item
+  RhsState* st = nullptr;           // device states (nrhs entries)
+  int state_index = 0;              // index of st[0] in the engine's state array
+  std::vector<RhsState> h_init;     // host staging of the initial states
+  long long started_block = 0;      // engine block count when the item was started
+  // server bookkeeping
+  uint64_t ticket = 0;
+  double t_submit = 0.0, t_done = 0.0;
+  size_t pool_off = 0, pool_len = 0;
+  int slot = -1;
+  std::vector<wd_solve_stats> stats;
+};
+
+// Runs CG for a changing set of items: one launch per CG phase covers every
+// item (grouped by nrhs, at most kMaxSlots per launch).
+class Engine {
+ public:
+  Engine(const wd_solve_params& p, hipStream_t s, RhsState* states, HopTimer* timer)
+      : p_(p), eo_(p.precond == WD_EO), stream_(s), states_(states), timer_(timer) {}
+  ~Engine() { drop_graph(); }
+  std::vector<EItem*> items;
+  long long blocks = 0;  // poll blocks enqueued so far
+
+  wd_status start_item(EItem* it);    // enqueue state init, source import, INIT
+  wd_status enqueue_block();          // K iterations with reliable updates
+  wd_status export_item(EItem* it);   // x = x_h (boundary layout)
+  void set_changed() { drop_graph(); }
+  int iters_per_block() const { return K_; }
+  RhsState* states() const { return states_; }
+
+ private:
+  struct Phase;
+  wd_status run_phase(const std::vector<EItem*>& list, const Phase& ph);
+  wd_status run_iteration();
+  wd_status run_reliable();
+  wd_status enqueue_direct();
+  void choose_block();
+  void drop_graph();
+  wd_solve_params p_;
+  bool eo_;
+  hipStream_t stream_;
+  RhsState* states_;
+  HopTimer* timer_;
+  int K_ = 8, ru_every_ = 8;
+  hipGraph_t graph_ = nullptr;
+  hipGraphExec_t gexec_ = nullptr;
+};
+
+// Fill stats from final device states (host copy).
+wd_status stats_from_state(const RhsState& s, double seconds, const HopTimer* t, wd_solve_stats& o);
+
+// Solve items to completion (no items join later).  Blocks the host.
+wd_status run_batch(std::vector<EItem>& items, const wd_solve_params& p, RhsState* states, hipStream_t stream,
+                    wd_solve_stats* stats);
+
+wd_status check_params(const wd_solve_params& p);
+wd_status check_lattice_for(const wd_lattice_s* lat, int prec, int precond);
+
+}  // namespace wd

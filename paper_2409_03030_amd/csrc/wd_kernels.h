@@ -1,0 +1,29 @@
+// Host-callable launchers of the device kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "wd_launch.h"
+
+namespace wd {
+
+// Stencil with epilogue `mode` (HopMode) at precision prec and link recon.
+hipError_t launch_hop(const Launch& L, int prec, int recon, int mode, hipStream_t stream);
+
+// CG vector kernel `mode` (BlasMode); prec is the precision of p (the
+// accumulation vectors x, r are F32 when prec is F16, else prec).
+hipError_t launch_blas(const Launch& L, int prec, int mode, hipStream_t stream);
+
+// complex128 boundary gauge field [mu][t][z][y][x][3][3] -> store.
+hipError_t launch_gauge_import(const void* U, void* store, const Geom& g, int prec, int recon,
+                               hipStream_t stream);
+
+// complex128 boundary spinors [rhs][t][z][y][x][4][3] <-> internal parity
+// blocks.  parities = 1: even sites only (block at dst); 2: both (even block
+// at dst, odd block at dst + pstride).
+hipError_t launch_spinor_import(const void* src, void* dst, size_t pstride, const Geom& g, int nrhs,
+                                int parities, int prec, hipStream_t stream);
+hipError_t launch_spinor_export(const void* src, size_t pstride, void* dst, const Geom& g, int nrhs,
+                                int parities, int prec, hipStream_t stream);
+
+}  // namespace wd

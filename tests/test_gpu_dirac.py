@@ -1,0 +1,193 @@
+"""GPU parity of the stencil operators against the CPU oracle (through the C ABI).
+
+Tolerances (norm-wise relative, ||y_gpu - y_oracle|| / ||y_oracle||):
+FP64 1e-12, FP32 1e-5, FP16 (per-site scaled spinors, half links) 3e-3.
+"""
+
+import numpy as np
+import pytest
+
+import oracle as O
+import qcdgen
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"f64": 1e-12, "f32": 1e-5, "f16": 3e-3}
+BC = (1, 1, 1, -1)
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _W():
+    from paper_2409_03030_amd import wdirac
+    return wdirac
+
+
+def _dev(a):
+    torch = _torch()
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+def _host(t):
+    _torch().cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def _rel(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+def _lattice(L, U, precs=(("f64", 18),), bc=BC):
+    W = _W()
+    lat = W.Lattice(L, bc)
+    Ud = _dev(U)
+    for prec, recon in precs:
+        lat.set_gauge(Ud, prec, recon)
+    return lat
+
+
+LATTICES = [(4, 4, 4, 4), (8, 8, 8, 8), (4, 6, 8, 10), (2, 2, 2, 2), (6, 2, 4, 2)]
+
+
+@pytest.mark.parametrize("L", LATTICES)
+@pytest.mark.parametrize("prec,recon", [("f64", 18), ("f64", 12), ("f32", 18), ("f32", 12), ("f16", 12), ("f16", 18)])
+def test_apply_D_full(L, prec, recon):
+    g = qcdgen.rng(101)
+    U = qcdgen.links_haar(L, g)
+    psi = qcdgen.gaussian_spinor(L, g)
+    kappa = 0.12
+    lat = _lattice(L, U, [(prec, recon)])
+    y = _host(lat.apply_D(_dev(psi), kappa, dagger=False, precond=0, prec=prec))
+    ref = O.apply_D(U, psi, kappa, BC)
+    assert _rel(y, ref) < TOL[prec]
+    yd = _host(lat.apply_D(_dev(psi), kappa, dagger=True, precond=0, prec=prec))
+    refd = O.apply_Ddag(U, psi, kappa, BC)
+    assert _rel(yd, refd) < TOL[prec]
+
+
+@pytest.mark.parametrize("L", LATTICES)
+@pytest.mark.parametrize("prec,recon", [("f64", 18), ("f32", 12), ("f16", 12)])
+def test_apply_Dhat_eo(L, prec, recon):
+    g = qcdgen.rng(103)
+    U = qcdgen.links_exp(L, 0.4, g)
+    psi = qcdgen.gaussian_spinor(L, g)
+    kappa = 0.137
+    lat = _lattice(L, U, [(prec, recon)])
+    e = O.even_mask(L)
+    y = _host(lat.apply_D(_dev(psi), kappa, dagger=False, precond=1, prec=prec))
+    ref = O.apply_Dhat(U, psi * e, kappa, BC)
+    assert np.abs(y * O.odd_mask(L)).max() == 0.0
+    assert _rel(y, ref) < TOL[prec]
+    yd = _host(lat.apply_D(_dev(psi), kappa, dagger=True, precond=1, prec=prec))
+    assert _rel(yd, O.apply_Dhat_dag(U, psi * e, kappa, BC)) < TOL[prec]
+    yn = _host(lat.apply_DdagD(_dev(psi), kappa, precond=1, prec=prec))
+    assert _rel(yn, O.apply_Ahat(U, psi * e, kappa, BC)) < 2 * TOL[prec]
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_apply_DdagD_full(prec):
+    L = (4, 4, 4, 8)
+    g = qcdgen.rng(107)
+    U = qcdgen.links_haar(L, g)
+    psi = qcdgen.gaussian_spinor(L, g)
+    lat = _lattice(L, U, [(prec, 18)])
+    y = _host(lat.apply_DdagD(_dev(psi), 0.13, precond=0, prec=prec))
+    assert _rel(y, O.apply_DdagD(U, psi, 0.13, BC)) < 2 * TOL[prec]
+
+
+@pytest.mark.parametrize("nrhs", [3, 12])
+def test_multi_rhs_matches_single(nrhs):
+    L = (4, 4, 6, 8)
+    g = qcdgen.rng(109)
+    U = qcdgen.links_exp(L, 0.3, g)
+    psi = qcdgen.gaussian_spinor(L, g, nrhs)
+    lat = _lattice(L, U, [("f64", 18), ("f32", 12)])
+    for prec in ("f64", "f32"):
+        y = _host(lat.apply_D(_dev(psi), 0.1365, precond=1, prec=prec))
+        for r in range(nrhs):
+            ys = _host(lat.apply_D(_dev(psi[r]), 0.1365, precond=1, prec=prec))
+            # identical arithmetic per site and rhs: bitwise equal
+            assert np.array_equal(y[r], ys)
+            assert _rel(y[r], O.apply_Dhat(U, psi[r] * O.even_mask(L), 0.1365, BC)) < TOL[prec]
+
+
+def test_recon12_equals_recon18_fp64():
+    L = (4, 4, 4, 4)
+    g = qcdgen.rng(113)
+    U = qcdgen.links_haar(L, g)
+    psi = qcdgen.gaussian_spinor(L, g)
+    W = _W()
+    l18 = _lattice(L, U, [("f64", 18)])
+    l12 = _lattice(L, U, [("f64", 12)])
+    a = _host(l18.apply_D(_dev(psi), 0.12, prec="f64"))
+    b = _host(l12.apply_D(_dev(psi), 0.12, prec="f64"))
+    assert _rel(a, b) < 1e-14
+
+
+def test_free_field_and_gamma5_hermiticity_on_gpu():
+    L = (4, 4, 4, 8)
+    U = qcdgen.links_unit(L)
+    lat = _lattice(L, U, [("f64", 18)])
+    kappa = 0.137
+    # plane wave: D e^{ipx} chi = e^{ipx} D(p) chi
+    p = np.array([2 * np.pi / 4, 0.0, 2 * np.pi * 3 / 4, np.pi * 3 / 8])
+    Lx, Ly, Lz, Lt = L
+    t, z, y, x = np.indices((Lt, Lz, Ly, Lx))
+    ph = np.exp(1j * (p[0] * x + p[1] * y + p[2] * z + p[3] * t))
+    g = qcdgen.rng(127)
+    chi = g.standard_normal((4, 3)) + 1j * g.standard_normal((4, 3))
+    psi = ph[..., None, None] * chi
+    Dp = (1 - 2 * kappa * np.cos(p).sum()) * np.eye(4) + 2j * kappa * sum(
+        O.GAMMA[m] * np.sin(p[m]) for m in range(4))
+    got = _host(lat.apply_D(_dev(psi), kappa, prec="f64"))
+    assert np.abs(got - ph[..., None, None] * (Dp @ chi)).max() < 1e-13
+    # gamma5-hermiticity through the GPU on random links
+    Uh = qcdgen.links_haar(L, g)
+    lat2 = _lattice(L, Uh, [("f64", 18)])
+    a = qcdgen.gaussian_spinor(L, g)
+    b = qcdgen.gaussian_spinor(L, g)
+    Da = _host(lat2.apply_D(_dev(a), kappa, prec="f64"))
+    Db = _host(lat2.apply_D(_dev(b), kappa, prec="f64"))
+    lhs = O.vdot(a, O.gamma5(Db))
+    rhs = np.conj(O.vdot(b, O.gamma5(Da)))
+    assert abs(lhs - rhs) < 1e-12 * abs(lhs)
+
+
+def test_gauge_covariance_on_gpu():
+    L = (4, 4, 2, 6)
+    g = qcdgen.rng(131)
+    U = qcdgen.links_exp(L, 0.4, g)
+    Om = qcdgen.random_gauge_transform(L, g)
+    psi = qcdgen.gaussian_spinor(L, g)
+    UO = np.empty_like(U)
+    for mu in range(4):
+        UO[mu] = np.einsum("...ab,...bc,...dc->...ad", Om, U[mu], np.conj(O.shift_forward(Om, mu)))
+    rot = lambda v: np.einsum("...ab,...sb->...sa", Om, v)
+    a = _host(_lattice(L, UO).apply_D(_dev(rot(psi)), 0.13, prec="f64"))
+    b = rot(_host(_lattice(L, U).apply_D(_dev(psi), 0.13, prec="f64")))
+    assert np.abs(a - b).max() < 1e-13
+
+
+@pytest.mark.parametrize("L,width,kappa", [((16, 16, 16, 32), 0.3, 0.1365), ((24, 24, 24, 48), 0.4, 0.137)])
+def test_full_size_sampled_sites(L, width, kappa):
+    """Full configuration sizes: 128 sampled output sites against the site-wise oracle."""
+    g = qcdgen.rng(qcdgen.CONFIG_SEED_BASE + 2)
+    U = qcdgen.links_exp(L, width, g)
+    psi = qcdgen.gaussian_spinor(L, g)
+    lat = _lattice(L, U, [("f64", 18), ("f32", 12)])
+    y64 = _host(lat.apply_D(_dev(psi), kappa, prec="f64"))
+    y32 = _host(lat.apply_D(_dev(psi), kappa, prec="f32"))
+    gs = qcdgen.rng(7)
+    sites = [tuple(int(gs.integers(0, L[m])) for m in range(4)) for _ in range(120)]
+    # include the corners where every boundary sign is taken
+    sites += [(0, 0, 0, 0), (L[0] - 1, L[1] - 1, L[2] - 1, L[3] - 1), (0, L[1] - 1, 0, L[3] - 1),
+              (L[0] - 1, 0, L[2] - 1, 0), (1, 0, 0, L[3] - 1), (0, 1, L[2] - 1, 0), (L[0] - 1, 1, 1, 1),
+              (2, L[1] - 1, 3, 0)]
+    ref = O.apply_D_sites(U, psi, kappa, BC, sites)
+    got64 = np.array([y64[s[3], s[2], s[1], s[0]] for s in sites])
+    got32 = np.array([y32[s[3], s[2], s[1], s[0]] for s in sites])
+    assert _rel(got64, ref) < 1e-12
+    assert _rel(got32, ref) < 1e-5
