@@ -101,6 +101,9 @@ typedef struct {
   double hop_ms;             /* with timing=1: summed duration of the stencil launches */
   int64_t hop_launches;      /* with timing=1: number of stencil launches timed */
   int64_t hop_site_updates;  /* stencil output sites x rhs processed by those launches */
+  double hop_bytes;          /* algorithmic bytes of those launches: each launch reads its 8 links per
+                                output site once (shared by the rhs), its input spinor once per site and
+                                rhs, and reads/writes its epilogue vectors once */
 } wd_solve_stats;
 
 /* ---- lattice ---------------------------------------------------------- */
@@ -191,15 +194,18 @@ wd_status wd_time_hop(wd_lattice lat, int32_t prec, int32_t nrhs, int32_t n,
                       void* ws, size_t ws_bytes, double* ms_per_launch, void* stream);
 
 /* Autotune the stencil launch shape (sites per workgroup, XCD-aware block
- * order) for this lattice, precision and nrhs by timing every candidate on
- * stream; the choice is kept in a process-wide table keyed by (dims, prec,
- * recon, nrhs) and used by every later launch.  Needs
- * wd_apply_workspace_bytes(lat, prec, nrhs).  Blocks the host.
- * *best_sites_per_block / *best_swizzle receive the choice (may be NULL). */
+ * order, number of threads the 8 hops of a site are split over) for this
+ * lattice, precision and nrhs by timing every candidate on stream; the choice
+ * is kept in a process-wide table keyed by (dims, prec, recon, nrhs) and used
+ * by every later launch.  Candidates with the same split must produce
+ * bit-identical output (checked).  Needs wd_apply_workspace_bytes(lat, prec,
+ * nrhs).  Blocks the host.  The best_* outputs receive the choice (may be NULL). */
 wd_status wd_autotune(wd_lattice lat, int32_t prec, int32_t nrhs, void* ws, size_t ws_bytes,
-                      int32_t* best_sites_per_block, int32_t* best_swizzle, void* stream);
+                      int32_t* best_sites_per_block, int32_t* best_swizzle, int32_t* best_split,
+                      void* stream);
 
-/* Read or write the tuning table as text ("Lx Ly Lz Lt prec recon nrhs sblk swz" lines).
+/* Read or write the tuning table as text ("Lx Ly Lz Lt prec recon nrhs sblk swz split"
+ * lines; split * sblk * nrhs <= 256, sblk * nrhs >= 64).
  * wd_tune_export returns the bytes needed (including the NUL) and writes at
  * most cap bytes into buf (may be NULL). */
 size_t wd_tune_export(char* buf, size_t cap);

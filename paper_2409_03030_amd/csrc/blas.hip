@@ -119,8 +119,10 @@ static hipError_t blas_mode(const Launch& L, int mode, hipStream_t stream) {
   return hipGetLastError();
 }
 
-hipError_t launch_blas(const Launch& L, int prec, int mode, hipStream_t stream) {
-  if (L.total_blocks <= 0) return hipSuccess;
+hipError_t launch_blas(const Launch& L0, int prec, int mode, hipStream_t stream) {
+  if (L0.total_blocks <= 0) return hipSuccess;
+  Launch L = L0;
+  L.split = 1;  // one thread per (site, rhs)
   if (prec == F64) return blas_mode<F64>(L, mode, stream);
   if (prec == F32) return blas_mode<F32>(L, mode, stream);
   if (prec == F16) return blas_mode<F16>(L, mode, stream);

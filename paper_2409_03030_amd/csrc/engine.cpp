@@ -133,7 +133,7 @@ wd_status Engine::run_phase(const std::vector<EItem*>& list, const Phase& ph0) {
       if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
       e = launch_hop(L, ph.prec, recon, ph.mode, stream_);
       if (e != hipSuccess) return hip_fail(e, "stencil launch");
-      e = timer_ ? timer_->end(stream_, sites) : hipSuccess;
+      e = timer_ ? timer_->end(stream_, sites, hop_launch_bytes(ph.prec, recon, ph.mode, sites, nrhs)) : hipSuccess;
       if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
     } else {
       hipError_t e = launch_blas(L, ph.prec, ph.mode, stream_);
@@ -290,6 +290,7 @@ wd_status stats_from_state(const RhsState& s, double seconds, const HopTimer* t,
   if (t && t->on) {
     o.hop_launches = (long long)(t->used / 2);
     o.hop_site_updates = t->site_updates;
+    o.hop_bytes = t->bytes;
   }
   if (s.state == ST_DONE) o.status = WD_OK;
   else if (s.state == ST_NONFINITE) o.status = WD_ENONFINITE;

@@ -19,7 +19,7 @@ namespace wd {
 
 template <int P> struct AccOf { static constexpr int value = P == F16 ? F32 : P; };
 
-template <int P, int R, int MODE>
+template <int P, int R, int MODE, int D>
 __global__ void __launch_bounds__(kBlock) hop_kernel(const Launch L) {
   using T = typename RealOf<P>::T;
   constexpr int A = AccOf<P>::value;
@@ -33,11 +33,41 @@ __global__ void __launch_bounds__(kBlock) hop_kernel(const Launch L) {
   const int par = t.parity;
   const size_t ne = (size_t)S.g.n * L.nrhs;
   const size_t e = (size_t)t.site * L.nrhs + t.rhs;
-  double v = 0.0;
-  if (t.valid && rhs_selected(S.st, L.mask, t.rhs)) {
+  const bool sel = t.valid && rhs_selected(S.st, L.mask, t.rhs);
+  spinor<T> acc;
+  if (sel) {
     const char* in = (const char*)S.in + (both ? (size_t)(1 - par) * S.vstride : 0);
-    spinor<T> acc;
-    hop_site<P, R>(S.g, par, t.site, t.rhs, L.nrhs, S.gauge, in, S.bc, L.g5in != 0, acc);
+    hop_part<P, R, D>(S.g, par, t.site, t.rhs, L.nrhs, S.gauge, in, S.bc, L.g5in != 0, t.part, acc);
+  }
+  if (D > 1) {
+    // parts 1..D-1 hand their sums to part 0, which adds them in part order
+    constexpr int kLds = D > 1 ? (D - 1) * 24 * (kBlock / D) : 1;
+    __shared__ T lds_acc[kLds];
+    const int per = L.sblk * L.nrhs;
+    const int loc = (int)threadIdx.x - t.part * per;
+    if (sel && t.part > 0) {
+      T* q = lds_acc + (size_t)(t.part - 1) * 24 * per + loc;
+#pragma unroll
+      for (int k = 0; k < 12; ++k) {
+        q[(2 * k) * per] = acc.c[k].re;
+        q[(2 * k + 1) * per] = acc.c[k].im;
+      }
+    }
+    __syncthreads();
+    if (sel && t.part == 0) {
+#pragma unroll
+      for (int pp = 1; pp < D; ++pp) {
+        const T* q = lds_acc + (size_t)(pp - 1) * 24 * per + loc;
+#pragma unroll
+        for (int k = 0; k < 12; ++k) {
+          acc.c[k].re += q[(2 * k) * per];
+          acc.c[k].im += q[(2 * k + 1) * per];
+        }
+      }
+    }
+  }
+  double v = 0.0;
+  if (sel && t.part == 0) {
     if (L.g5out) gamma5_inplace(acc);
     if (MODE == HOP_PLAIN) {
       char* out = (char*)S.out + (both ? (size_t)par * S.vstride : 0);
@@ -86,21 +116,32 @@ __global__ void __launch_bounds__(kBlock) hop_kernel(const Launch L) {
   if (L.fin != FIN_NONE) reduce_and_finalize(L, S, t, v);
 }
 
-template <int P, int R, int MODE>
+template <int P, int R, int MODE, int D>
 static hipError_t launch_one(const Launch& L, hipStream_t stream) {
-  dim3 grid((unsigned)L.total_blocks), block((unsigned)(L.sblk * L.nrhs));
-  hipLaunchKernelGGL((hop_kernel<P, R, MODE>), grid, block, 0, stream, L);
+  dim3 grid((unsigned)L.total_blocks), block((unsigned)(D * L.sblk * L.nrhs));
+  hipLaunchKernelGGL((hop_kernel<P, R, MODE, D>), grid, block, 0, stream, L);
   return hipGetLastError();
+}
+
+template <int P, int R, int MODE>
+static hipError_t launch_split(const Launch& L, hipStream_t stream) {
+  switch (L.split) {
+    case 1: return launch_one<P, R, MODE, 1>(L, stream);
+    case 2: return launch_one<P, R, MODE, 2>(L, stream);
+    case 4: return launch_one<P, R, MODE, 4>(L, stream);
+  }
+  return hipErrorInvalidValue;
 }
 
 template <int P, int R>
 static hipError_t launch_mode(const Launch& L, int mode, hipStream_t stream) {
+  if (L.split * L.sblk * L.nrhs > kBlock) return hipErrorInvalidValue;
   switch (mode) {
-    case HOP_PLAIN: return launch_one<P, R, HOP_PLAIN>(L, stream);
-    case HOP_XPAY: return launch_one<P, R, HOP_XPAY>(L, stream);
-    case HOP_CGR: return launch_one<P, R, HOP_CGR>(L, stream);
+    case HOP_PLAIN: return launch_split<P, R, HOP_PLAIN>(L, stream);
+    case HOP_XPAY: return launch_split<P, R, HOP_XPAY>(L, stream);
+    case HOP_CGR: return launch_split<P, R, HOP_CGR>(L, stream);
     case HOP_RESID:
-      if constexpr (P == F64) return launch_one<P, R, HOP_RESID>(L, stream);
+      if constexpr (P == F64) return launch_split<P, R, HOP_RESID>(L, stream);
       return hipErrorInvalidValue;
   }
   return hipErrorInvalidValue;

@@ -88,15 +88,24 @@ int default_sblk(int nrhs) {
   return s;
 }
 
-static bool valid_sblk(int sblk, int nrhs) {
-  return sblk >= 1 && (sblk & (sblk - 1)) == 0 && sblk * nrhs <= kBlock && sblk * nrhs >= 32;
+// A block holds split * sblk * nrhs threads (at most kBlock); a part of the
+// split covers whole waves; the reduction needs at least one full wave.
+bool valid_tune(const Tune& t, int nrhs) {
+  const int sb = t.sblk;
+  if (sb < 1 || (sb & (sb - 1)) != 0) return false;
+  if (t.split != 1 && t.split != 2 && t.split != 4) return false;
+  if (t.swz != 0 && t.swz != 1) return false;
+  const int per = sb * nrhs;
+  if (per < 64 || t.split * per > kBlock) return false;
+  if (t.split > 1 && per % 64 != 0) return false;
+  return true;
 }
 
 Tune tune_lookup(const wd_lattice_s* lat, int prec, int recon, int nrhs) {
   std::lock_guard<std::mutex> lk(g_tune_mu);
   auto it = g_tune.find(tkey(lat, prec, recon, nrhs));
   if (it != g_tune.end()) return it->second;
-  return Tune{default_sblk(nrhs), 1};
+  return Tune{default_sblk(nrhs), 1, 1};
 }
 
 void tune_store(const wd_lattice_s* lat, int prec, int recon, int nrhs, Tune t) {
@@ -129,6 +138,7 @@ Launch base_launch(int nrhs, const Tune& t, int parity) {
   L.nrhs = nrhs;
   L.sblk = t.sblk;
   L.swz = t.swz;
+  L.split = t.split;
   L.parity = parity;
   return L;
 }
@@ -149,12 +159,29 @@ hipError_t HopTimer::begin(hipStream_t s) {
   return hipEventRecord(ev[used], s);
 }
 
-hipError_t HopTimer::end(hipStream_t s, long long sites) {
+hipError_t HopTimer::end(hipStream_t s, long long sites, double b) {
   if (!on) return hipSuccess;
   hipError_t r = hipEventRecord(ev[used + 1], s);
   used += 2;
   site_updates += sites;
+  bytes += b;
   return r;
+}
+
+double hop_launch_bytes(int prec, int recon, int mode, long long sites, int nrhs) {
+  const double link = (prec == F64 ? 16.0 : prec == F32 ? 8.0 : 4.0) * (recon == 12 ? 6 : 9);
+  const double sp = prec == F64 ? 192.0 : prec == F32 ? 96.0 : 52.0;  // F16: 48 B data + 4 B scale
+  const int A = acc_prec(prec);
+  const double sa = A == F64 ? 192.0 : 96.0;
+  double vec = 0.0;
+  switch (mode) {
+    case HOP_PLAIN: vec = 2 * sp; break;                  // in, out
+    case HOP_XPAY: vec = 3 * sp; break;                   // in, aux, out
+    case HOP_CGR: vec = 2 * sp + 2 * sa; break;           // in, aux, r read + write
+    case HOP_RESID: vec = 2 * sp + 2 * 192.0; break;      // in, aux, b, r_h
+  }
+  const double site_sets = (double)sites / nrhs;           // sites counts site x rhs
+  return site_sets * 8 * link + (double)sites * vec;
 }
 
 double HopTimer::total_ms() {
@@ -484,7 +511,7 @@ wd_status wd_time_hop(wd_lattice lat, int32_t prec, int32_t nrhs, int32_t n, voi
 }
 
 wd_status wd_autotune(wd_lattice lat, int32_t prec, int32_t nrhs, void* ws, size_t ws_bytes,
-                      int32_t* best_sites_per_block, int32_t* best_swizzle, void* stream) {
+                      int32_t* best_sites_per_block, int32_t* best_swizzle, int32_t* best_split, void* stream) {
   wd_status s = check_lattice_for(lat, prec, WD_EO);
   if (s != WD_OK) return s;
   if (!ws) return fail(WD_EINVAL, "null workspace");
@@ -498,33 +525,36 @@ wd_status wd_autotune(wd_lattice lat, int32_t prec, int32_t nrhs, void* ws, size
   for (size_t i = 0; i < vb; ++i) pat[i] = (unsigned char)((i * 2654435761u) >> 13) & 0x3f;
   WD_HIP(hipMemcpyAsync(w, pat.data(), vb, hipMemcpyHostToDevice, st));
   WD_HIP(hipStreamSynchronize(st));
-  const int recon = lat->store[prec].recon;
-  std::vector<unsigned char> ref, got;
+  std::vector<unsigned char> ref[5], got;
   double best = 1e30;
-  Tune bt{default_sblk(nrhs), 1};
-  for (int sblk = 1; sblk <= kBlock; sblk *= 2) {
-    if (!valid_sblk(sblk, nrhs)) continue;
-    for (int swz = 0; swz <= 1; ++swz) {
-      Tune t{sblk, swz};
-      WD_HIP(hipMemsetAsync(w + 2 * vb, 0, vb, st));
-      double ms = 0.0;
-      if ((s = time_hop_shape(lat, prec, nrhs, 20, t, w, &ms, st)) != WD_OK) return s;
-      // every shape must produce the same bytes: the per-site arithmetic does not depend on tiling
-      got.resize(vb);
-      WD_HIP(hipMemcpy(got.data(), w + 2 * vb, vb, hipMemcpyDeviceToHost));
-      if (ref.empty()) ref = got;
-      else if (memcmp(ref.data(), got.data(), vb) != 0)
-        return fail(WD_EDEVICE, "tuning candidate sblk=%d swz=%d changed the stencil output", sblk, swz);
-      if (ms < best) {
-        best = ms;
-        bt = t;
+  Tune bt{default_sblk(nrhs), 1, 1};
+  for (int split = 1; split <= 4; split *= 2) {
+    for (int sblk = 1; sblk <= kBlock; sblk *= 2) {
+      for (int swz = 0; swz <= 1; ++swz) {
+        Tune t{sblk, swz, split};
+        if (!valid_tune(t, nrhs)) continue;
+        WD_HIP(hipMemsetAsync(w + 2 * vb, 0, vb, st));
+        double ms = 0.0;
+        if ((s = time_hop_shape(lat, prec, nrhs, 20, t, w, &ms, st)) != WD_OK) return s;
+        // within one split the per-site arithmetic does not depend on the tiling:
+        // every shape must produce the same bytes
+        got.resize(vb);
+        WD_HIP(hipMemcpy(got.data(), w + 2 * vb, vb, hipMemcpyDeviceToHost));
+        if (ref[split].empty()) ref[split] = got;
+        else if (memcmp(ref[split].data(), got.data(), vb) != 0)
+          return fail(WD_EDEVICE, "tuning candidate sblk=%d swz=%d split=%d changed the stencil output", sblk, swz,
+                      split);
+        if (ms < best) {
+          best = ms;
+          bt = t;
+        }
       }
     }
   }
-  (void)recon;
   tune_store(lat, prec, lat->store[prec].recon, nrhs, bt);
   if (best_sites_per_block) *best_sites_per_block = bt.sblk;
   if (best_swizzle) *best_swizzle = bt.swz;
+  if (best_split) *best_split = bt.split;
   return WD_OK;
 }
 
@@ -536,7 +566,7 @@ size_t wd_tune_export(char* buf, size_t cap) {
       const TuneKey& k = kv.first;
       os << std::get<0>(k) << ' ' << std::get<1>(k) << ' ' << std::get<2>(k) << ' ' << std::get<3>(k) << ' '
          << std::get<4>(k) << ' ' << std::get<5>(k) << ' ' << std::get<6>(k) << ' ' << kv.second.sblk << ' '
-         << kv.second.swz << '\n';
+         << kv.second.swz << ' ' << kv.second.split << '\n';
     }
   }
   const std::string s = os.str();
@@ -556,12 +586,12 @@ wd_status wd_tune_import(const char* text) {
   while (std::getline(is, line)) {
     if (line.empty()) continue;
     std::istringstream ls(line);
-    int v[9];
-    for (int i = 0; i < 9; ++i)
+    int v[10];
+    for (int i = 0; i < 10; ++i)
       if (!(ls >> v[i])) return fail(WD_EINVAL, "malformed tuning line '%s'", line.c_str());
-    if (!valid_sblk(v[7], v[6]) || (v[8] != 0 && v[8] != 1))
-      return fail(WD_EINVAL, "invalid tuning values in '%s'", line.c_str());
-    rows.push_back({TuneKey(v[0], v[1], v[2], v[3], v[4], v[5], v[6]), Tune{v[7], v[8]}});
+    const Tune t{v[7], v[8], v[9]};
+    if (!valid_tune(t, v[6])) return fail(WD_EINVAL, "invalid tuning values in '%s'", line.c_str());
+    rows.push_back({TuneKey(v[0], v[1], v[2], v[3], v[4], v[5], v[6]), t});
   }
   std::lock_guard<std::mutex> lk(g_tune_mu);
   for (auto& r : rows) g_tune[r.first] = r.second;

@@ -450,20 +450,50 @@ WD_HD void hop_dir(const Geom& g, const Coord& k, int parity, int s, int rhs, in
   accumulate<MU, DIR>(acc, gh);
 }
 
+// Both hops along direction MU (forward then backward).
+template <int P, int R, int MU>
+WD_HD void hop_mu(const Geom& g, const Coord& k, int parity, int s, int rhs, int nrhs, const char* gauge,
+                  const void* in, const float bc[4], bool g5in, spinor<typename RealOf<P>::T>& acc) {
+  hop_dir<P, R, MU, +1>(g, k, parity, s, rhs, nrhs, gauge, in, bc[MU], g5in, acc);
+  hop_dir<P, R, MU, -1>(g, k, parity, s, rhs, nrhs, gauge, in, bc[MU], g5in, acc);
+}
+
+// The share `part` of the 8 hops when they are split over D threads:
+// D = 1 all directions, D = 2 (x,y) / (z,t), D = 4 one direction each.
+template <int P, int R, int D>
+WD_HD void hop_part(const Geom& g, int parity, int s, int rhs, int nrhs, const char* gauge, const void* in,
+                    const float bc[4], bool g5in, int part, spinor<typename RealOf<P>::T>& acc) {
+  Coord k = site_coord(g, parity, s);
+  spinor_zero(acc);
+  if (D == 1) {
+    hop_mu<P, R, 0>(g, k, parity, s, rhs, nrhs, gauge, in, bc, g5in, acc);
+    hop_mu<P, R, 1>(g, k, parity, s, rhs, nrhs, gauge, in, bc, g5in, acc);
+    hop_mu<P, R, 2>(g, k, parity, s, rhs, nrhs, gauge, in, bc, g5in, acc);
+    hop_mu<P, R, 3>(g, k, parity, s, rhs, nrhs, gauge, in, bc, g5in, acc);
+  } else if (D == 2) {
+    if (part == 0) {
+      hop_mu<P, R, 0>(g, k, parity, s, rhs, nrhs, gauge, in, bc, g5in, acc);
+      hop_mu<P, R, 1>(g, k, parity, s, rhs, nrhs, gauge, in, bc, g5in, acc);
+    } else {
+      hop_mu<P, R, 2>(g, k, parity, s, rhs, nrhs, gauge, in, bc, g5in, acc);
+      hop_mu<P, R, 3>(g, k, parity, s, rhs, nrhs, gauge, in, bc, g5in, acc);
+    }
+  } else {
+    switch (part) {
+      case 0: hop_mu<P, R, 0>(g, k, parity, s, rhs, nrhs, gauge, in, bc, g5in, acc); break;
+      case 1: hop_mu<P, R, 1>(g, k, parity, s, rhs, nrhs, gauge, in, bc, g5in, acc); break;
+      case 2: hop_mu<P, R, 2>(g, k, parity, s, rhs, nrhs, gauge, in, bc, g5in, acc); break;
+      default: hop_mu<P, R, 3>(g, k, parity, s, rhs, nrhs, gauge, in, bc, g5in, acc); break;
+    }
+  }
+}
+
+// The whole hopping term at one site (all 8 hops in one thread).
 template <int P, int R>
 WD_HD void hop_site(const Geom& g, int parity, int s, int rhs, int nrhs, const char* gauge,
                     const void* in, const float bc[4], bool g5in,
                     spinor<typename RealOf<P>::T>& acc) {
-  Coord k = site_coord(g, parity, s);
-  spinor_zero(acc);
-  hop_dir<P, R, 0, +1>(g, k, parity, s, rhs, nrhs, gauge, in, bc[0], g5in, acc);
-  hop_dir<P, R, 0, -1>(g, k, parity, s, rhs, nrhs, gauge, in, bc[0], g5in, acc);
-  hop_dir<P, R, 1, +1>(g, k, parity, s, rhs, nrhs, gauge, in, bc[1], g5in, acc);
-  hop_dir<P, R, 1, -1>(g, k, parity, s, rhs, nrhs, gauge, in, bc[1], g5in, acc);
-  hop_dir<P, R, 2, +1>(g, k, parity, s, rhs, nrhs, gauge, in, bc[2], g5in, acc);
-  hop_dir<P, R, 2, -1>(g, k, parity, s, rhs, nrhs, gauge, in, bc[2], g5in, acc);
-  hop_dir<P, R, 3, +1>(g, k, parity, s, rhs, nrhs, gauge, in, bc[3], g5in, acc);
-  hop_dir<P, R, 3, -1>(g, k, parity, s, rhs, nrhs, gauge, in, bc[3], g5in, acc);
+  hop_part<P, R, 1>(g, parity, s, rhs, nrhs, gauge, in, bc, g5in, 0, acc);
 }
 
 }  // namespace wd

@@ -40,10 +40,17 @@ size_t vec_bytes(int prec, size_t n, int nrhs);
 size_t gauge_bytes(const Geom& g, int prec, int recon);
 inline int acc_prec(int prec) { return prec == F16 ? F32 : prec; }
 
+// Algorithmic bytes of one stencil launch over `sites` output sites with
+// nrhs fields: 8 links per site (shared by the rhs), the input spinor once,
+// and the epilogue vectors of the mode once each.
+double hop_launch_bytes(int prec, int recon, int mode, long long sites, int nrhs);
+
 struct Tune {
-  int sblk;  // sites per block (power of two, sblk * nrhs <= kBlock)
-  int swz;   // XCD-aware block order
+  int sblk;   // sites per block (power of two, split * sblk * nrhs <= kBlock)
+  int swz;    // XCD-aware block order
+  int split;  // threads per (site, rhs) in the stencil: 1, 2 or 4
 };
+bool valid_tune(const Tune& t, int nrhs);
 Tune tune_lookup(const wd_lattice_s* lat, int prec, int recon, int nrhs);
 void tune_store(const wd_lattice_s* lat, int prec, int recon, int nrhs, Tune t);
 int default_sblk(int nrhs);
@@ -60,8 +67,9 @@ struct HopTimer {
   std::vector<hipEvent_t> ev;
   size_t used = 0;
   long long site_updates = 0;
+  double bytes = 0.0;
   hipError_t begin(hipStream_t s);
-  hipError_t end(hipStream_t s, long long sites);
+  hipError_t end(hipStream_t s, long long sites, double bytes);
   double total_ms();
   void release();
 };

@@ -13,6 +13,7 @@ struct Tile {
   int site;     // checkerboard index of this thread's site (may be >= n: idle)
   int rhs;
   int lblk;     // block index within the slot
+  int part;     // which share of the hops this thread computes (stencil split)
   bool valid;   // site < n
 };
 
@@ -45,10 +46,13 @@ __device__ __forceinline__ Tile make_tile(const Launch& L) {
   } else {
     t.parity = L.parity;
   }
+  const int per_part = L.sblk * L.nrhs;
   const int tid = (int)threadIdx.x;
-  t.site = lb * L.sblk + tid / L.nrhs;
-  t.rhs = tid % L.nrhs;
-  t.valid = (tid < L.sblk * L.nrhs) && (t.site < S.g.n);
+  t.part = tid / per_part;
+  const int loc = tid - t.part * per_part;
+  t.site = lb * L.sblk + loc / L.nrhs;
+  t.rhs = loc % L.nrhs;
+  t.valid = (t.part < (L.split > 0 ? L.split : 1)) && (t.site < S.g.n);
   return t;
 }
 
@@ -165,6 +169,21 @@ __device__ void finalize_rhs(int fin, RhsState& s, double sum) {
 // then the last arriving block of the slot sums the block partials in a
 // fixed order and runs finalize_rhs.  Deterministic: the result does not
 // depend on block scheduling.  All threads of the block must call this.
+//
+// Cross-block visibility without fences: a release fence at device scope
+// writes back the whole L2 of the XCD, which costs more than the stencil
+// itself when every block does it.  Instead the partials are written with
+// device-scope atomic stores (coherent across the XCDs' L2s), the block
+// waits for them to complete before it counts itself in with a device-scope
+// atomic, and the last block reads the partials with device-scope atomic
+// loads.  The state it writes is read by later launches only.
+__device__ __forceinline__ void store_partial(double* p, double v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ double load_partial(const double* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 __device__ void reduce_and_finalize(const Launch& L, const Slot& S, const Tile& t, double v) {
   __shared__ double lds[kBlock];
   __shared__ int is_last;
@@ -172,36 +191,68 @@ __device__ void reduce_and_finalize(const Launch& L, const Slot& S, const Tile& 
   const int nr = L.nrhs;
   const int sb = L.sblk;
   const int nthr = sb * nr;
-  if (tid < nthr) lds[tid] = v;
-  __syncthreads();
   const int sl = tid / nr;
-  for (int w = sb >> 1; w > 0; w >>= 1) {
-    if (sl < w) lds[tid] += lds[tid + w * nr];
+  if (nr == 1) {
+    // wave sums by butterfly shuffles, then the block's waves in order
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    if ((tid & 63) == 0) lds[tid >> 6] = v;
     __syncthreads();
+    if (tid == 0) {
+      double s = 0.0;
+      const int nw = (nthr + 63) >> 6;
+      for (int w = 0; w < nw; ++w) s += lds[w];
+      lds[0] = s;
+    }
+    __syncthreads();
+  } else {
+    if (tid < nthr) lds[tid] = v;
+    __syncthreads();
+    for (int w = sb >> 1; w > 0; w >>= 1) {
+      if (sl < w) lds[tid] += lds[tid + w * nr];
+      __syncthreads();
+    }
   }
-  if (tid < nr) S.partial[(size_t)t.lblk * nr + tid] = lds[tid];
-  __threadfence();
+  if (tid < nr) store_partial(&S.partial[(size_t)t.lblk * nr + tid], lds[tid]);
+  // the partial stores must have completed before the arrival is counted
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  __builtin_amdgcn_s_waitcnt(0);
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
   __syncthreads();
   if (tid == 0) {
-    unsigned prev = atomicAdd(S.counter, 1u);
+    unsigned prev = __hip_atomic_fetch_add(S.counter, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     is_last = (prev == (unsigned)(S.nblk - 1));
   }
   __syncthreads();
   if (!is_last) return;
-  __threadfence();
   double acc = 0.0;
   if (tid < nthr) {
-    const volatile double* part = S.partial;
-    for (int b = sl; b < S.nblk; b += sb) acc += part[(size_t)b * nr + (tid % nr)];
-    lds[tid] = acc;
+    for (int b = sl; b < S.nblk; b += sb) acc += load_partial(&S.partial[(size_t)b * nr + (tid % nr)]);
   }
+  if (nr == 1) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+    __syncthreads();
+    if ((tid & 63) == 0) lds[tid >> 6] = acc;
+    __syncthreads();
+    if (tid == 0) {
+      double s = 0.0;
+      const int nw = (nthr + 63) >> 6;
+      for (int w = 0; w < nw; ++w) s += lds[w];
+      if (S.st != nullptr) finalize_rhs(L.fin, S.st[0], s);
+      __hip_atomic_store(S.counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    return;
+  }
+  __syncthreads();
+  if (tid < nthr) lds[tid] = acc;
   __syncthreads();
   for (int w = sb >> 1; w > 0; w >>= 1) {
     if (sl < w) lds[tid] += lds[tid + w * nr];
     __syncthreads();
   }
   if (tid < nr && S.st != nullptr) finalize_rhs(L.fin, S.st[tid], lds[tid]);
-  if (tid == 0) atomicExch(S.counter, 0u);
+  if (tid == 0) __hip_atomic_store(S.counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 }  // namespace wd

@@ -5,7 +5,9 @@
 // as (slot, parity, block of sblk sites) x nrhs threads: thread t of a block
 // handles site t / nrhs of the block and rhs t % nrhs, so the nrhs threads of
 // a site sit in adjacent lanes, read the same links (one memory request per
-// wave) and adjacent 16-byte spinor chunks.
+// wave) and adjacent 16-byte spinor chunks.  The stencil may also split the
+// 8 hops of a site over `split` threads (part-major: part p is threads
+// [p*sblk*nrhs, (p+1)*sblk*nrhs)), which multiplies the waves in flight.
 #pragma once
 
 #include "wd_device.h"
@@ -67,7 +69,8 @@ struct Launch {
   Slot s[kMaxSlots];
   int nslots;
   int nrhs;
-  int sblk;             // sites per block (power of two); threads = sblk * nrhs
+  int sblk;             // sites per block (power of two)
+  int split;            // threads per (site, rhs) in the stencil: 1, 2 or 4 (each takes 8/split hops)
   int parity;           // output parity 0 / 1, or 2 = both (input = the other one)
   int g5in, g5out;
   int mask;             // Mask

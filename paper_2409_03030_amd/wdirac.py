@@ -58,6 +58,7 @@ class SolveStats(C.Structure):
         ("hop_ms", C.c_double),
         ("hop_launches", C.c_int64),
         ("hop_site_updates", C.c_int64),
+        ("hop_bytes", C.c_double),
     ]
 
     def as_dict(self):
@@ -94,7 +95,7 @@ _SIGS = [
                                    C.POINTER(SolveStats), _P]),
     ("wd_time_hop", C.c_int32, [_P, C.c_int32, C.c_int32, C.c_int32, _P, C.c_size_t, C.POINTER(C.c_double), _P]),
     ("wd_autotune", C.c_int32, [_P, C.c_int32, C.c_int32, _P, C.c_size_t, C.POINTER(C.c_int32),
-                                C.POINTER(C.c_int32), _P]),
+                                C.POINTER(C.c_int32), C.POINTER(C.c_int32), _P]),
     ("wd_tune_export", C.c_size_t, [C.c_char_p, C.c_size_t]),
     ("wd_tune_import", C.c_int32, [C.c_char_p]),
     ("wd_server_create", C.c_int32, [C.POINTER(C.c_void_p), _P, C.c_size_t, C.c_int32, C.POINTER(SolveParams), _P]),
@@ -291,10 +292,22 @@ class Lattice:
         nb = int(lib().wd_apply_workspace_bytes(self.handle, PREC[prec], nrhs))
         dev = next(iter(self.stores.values())).device
         ws = self._workspace(nb, dev, ("apply", PREC[prec], nrhs))
-        sb, sw = C.c_int32(), C.c_int32()
+        sb, sw, sp = C.c_int32(), C.c_int32(), C.c_int32()
         _check(lib().wd_autotune(self.handle, PREC[prec], nrhs, _ptr(ws), ws.numel(), C.byref(sb), C.byref(sw),
-                                 _stream(stream)), "wd_autotune")
-        return sb.value, sw.value
+                                 C.byref(sp), _stream(stream)), "wd_autotune")
+        return sb.value, sw.value, sp.value
+
+
+def tune_import(text: str):
+    """Load tuning lines "Lx Ly Lz Lt prec recon nrhs sblk swz split"."""
+    _check(lib().wd_tune_import(text.encode()), "wd_tune_import")
+
+
+def tune_export() -> str:
+    n = lib().wd_tune_export(None, 0)
+    buf = C.create_string_buffer(n)
+    lib().wd_tune_export(buf, n)
+    return buf.value.decode()
 
 
 def solve_batch(requests, params=None, stream=None, check=True):

@@ -83,15 +83,17 @@ def test_workspace_sizes_scale_with_nrhs():
 
 def test_tuning_table_roundtrip():
     lib = W.lib()
-    assert lib.wd_tune_import(b"16 16 16 32 0 18 1 64 1\n24 24 24 48 1 12 12 16 0\n") == W.WD_OK
+    assert lib.wd_tune_import(b"16 16 16 32 0 18 1 64 1 2\n24 24 24 48 1 12 12 16 0 1\n") == W.WD_OK
     n = lib.wd_tune_export(None, 0)
     buf = C.create_string_buffer(n)
     lib.wd_tune_export(buf, n)
     txt = buf.value.decode()
-    assert "16 16 16 32 0 18 1 64 1" in txt
-    assert "24 24 24 48 1 12 12 16 0" in txt
+    assert "16 16 16 32 0 18 1 64 1 2" in txt
+    assert "24 24 24 48 1 12 12 16 0 1" in txt
     assert lib.wd_tune_import(b"1 2 3\n") == W.WD_EINVAL
-    assert lib.wd_tune_import(b"16 16 16 32 0 18 1 3 1\n") == W.WD_EINVAL  # not a power of two
+    assert lib.wd_tune_import(b"16 16 16 32 0 18 1 3 1 1\n") == W.WD_EINVAL   # not a power of two
+    assert lib.wd_tune_import(b"16 16 16 32 0 18 1 128 1 4\n") == W.WD_EINVAL  # 512 threads
+    assert lib.wd_tune_import(b"16 16 16 32 0 18 1 64 1 3\n") == W.WD_EINVAL   # split 3
 
 
 def test_status_strings():

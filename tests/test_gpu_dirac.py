@@ -191,3 +191,33 @@ def test_full_size_sampled_sites(L, width, kappa):
     got32 = np.array([y32[s[3], s[2], s[1], s[0]] for s in sites])
     assert _rel(got64, ref) < 1e-12
     assert _rel(got32, ref) < 1e-5
+
+
+@pytest.mark.parametrize("nrhs", [1, 4])
+@pytest.mark.parametrize("split,sblk,swz", [(1, 64, 0), (1, 256, 1), (2, 64, 1), (2, 128, 0), (4, 64, 1)])
+def test_launch_shapes_match_oracle(nrhs, split, sblk, swz):
+    """Every stencil launch shape (hop split, block size, XCD order) gives the oracle's D_hat."""
+    W = _W()
+    L = (8, 4, 6, 8)   # dims used by no other test: the tuning table is process-wide
+    sb = sblk if nrhs == 1 else max(16, sblk // 4)
+    if split * sb * nrhs > 256:
+        pytest.skip("block too large")
+    g = qcdgen.rng(137)
+    U = qcdgen.links_exp(L, 0.4, g)
+    psi = qcdgen.gaussian_spinor(L, g, nrhs)
+    lat = _lattice(L, U, [("f64", 18), ("f32", 12), ("f16", 12)])
+    lines = "".join(f"{L[0]} {L[1]} {L[2]} {L[3]} {p} {r} {nrhs} {sb} {swz} {split}\n"
+                    for p, r in ((0, 18), (1, 12), (2, 12)))
+    W.tune_import(lines)
+    e = O.even_mask(L)
+    for prec in ("f64", "f32", "f16"):
+        y = _host(lat.apply_D(_dev(psi), 0.1365, precond=1, prec=prec))
+        yd = _host(lat.apply_DdagD(_dev(psi), 0.1365, precond=1, prec=prec))
+        for r in range(nrhs):
+            assert _rel(y[r], O.apply_Dhat(U, psi[r] * e, 0.1365, BC)) < TOL[prec]
+            assert _rel(yd[r], O.apply_Ahat(U, psi[r] * e, 0.1365, BC)) < 2 * TOL[prec]
+    # and a solve through the same shapes
+    b = np.ascontiguousarray(psi[0])
+    x, st = lat.solve(_dev(b), 0.1365, W.default_params(inner="f16", delta=1e-2))
+    assert st[0]["status"] == 0
+    assert O.residual_DdagD(U, _host(x), b, 0.1365, BC, True) <= 1e-10
