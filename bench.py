@@ -223,6 +223,284 @@ def bench_default(args):
     print(json.dumps(out), flush=True)
 
 
+# ---------------------------------------------------------------------------
+# other workloads
+# ---------------------------------------------------------------------------
+def _common_out(args, metric_value, unit, ms_per_step, dtype, config, extra):
+    out = {
+        "metric": METRIC,
+        "value": metric_value,
+        "unit": unit,
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": dtype,
+        "data": "synthetic",
+        "config": config,
+    }
+    out.update(extra)
+    return out
+
+
+def bench_cfg1(args):
+    """4^4 Haar links, kappa 0.12, unpreconditioned: D once + plain FP64 CG."""
+    import torch
+    import qcdgen
+    from paper_2409_03030_amd import wdirac as W
+    L, kappa = (4, 4, 4, 4), 0.12
+    U = qcdgen.links_haar(L, qcdgen.rng(qcdgen.CONFIG_SEED_BASE + 0))
+    b = qcdgen.gaussian_spinor(L, qcdgen.rng(qcdgen.CONFIG_SEED_BASE + 100))
+    Ud, bd = torch.from_numpy(U).cuda(), torch.from_numpy(b).cuda()
+    lat = W.Lattice(L, BC)
+    lat.set_gauge(Ud, "f64", 18)
+    p = W.default_params(precond=W.FULL)
+    y = lat.apply_D(bd, kappa, precond=W.FULL)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(100):
+        lat.apply_D(bd, kappa, precond=W.FULL, out=y)
+    torch.cuda.synchronize()
+    d_ms = (time.perf_counter() - t0) / 100 * 1e3
+    x, st, dt = time_solves(lat, Ud, bd, kappa, p, args.steps, args.warmup)
+    V = 256
+    return _common_out(args, dw_flops(st, V // 2, eo=False) / dt / 1e9, "GFLOP/s", dt * 1e3, "f64",
+                       {"workload": "4^4 Haar SU(3), kappa=0.12, unpreconditioned, plain FP64 CG to 1e-10",
+                        "lattice": list(L), "kappa": kappa},
+                       {"time_to_solution_ms": dt * 1e3, "iters": st["iters"], "true_resid": st["true_resid"],
+                        "apply_D_ms": d_ms, "note": "latency-bound (128 sites per parity); not a roofline point"})
+
+
+def bench_cfg3(args):
+    """24^3x48, width 0.4, kappa 0.137: FP32 / FP16 inner with recon-12 links, FP64 reliable updates."""
+    import torch
+    from paper_2409_03030_amd import wdirac as W
+    log("generating 24^3x48 workload ...")
+    L, width, kappa, U, b = make_workload("cfg3")
+    half = L[0] * L[1] * L[2] * L[3] // 2
+    Ud, bd = torch.from_numpy(U).cuda(), torch.from_numpy(b).cuda()
+    del U
+    lat = W.Lattice(L, BC)
+    for prec, recon in (("f64", 18), ("f32", 12), ("f16", 12)):
+        lat.set_gauge(Ud, prec, recon)
+        sb, sw, sp = lat.autotune(prec, 1)
+        log(f"autotune {prec}: sites/block {sb}, xcd swizzle {sw}, hop split {sp}")
+    res = {}
+    x64 = None
+    for name, p in (("f64", W.default_params()),
+                    ("f32", W.default_params(inner="f32", delta=1e-2)),
+                    ("f16", W.default_params(inner="f16", delta=1e-2))):
+        x, st, dt = time_solves(lat, Ud, bd, kappa, p, args.steps if name != "f64" else max(1, args.steps // 2), 1)
+        if st["status"] != 0:
+            raise SystemExit(f"{name} solve failed: {st}")
+        roof = instrumented(lat, bd, kappa, p)
+        r = {"time_to_solution_ms": dt * 1e3, "iters": st["iters"], "reliable_updates": st["reliable_updates"],
+             "true_resid": st["true_resid"], "stencil_gbs": roof["achieved_gbs"],
+             "stencil_ms_avg": roof["hop_ms_avg"], "dw_gflops": dw_flops(st, half) / dt / 1e9}
+        if x64 is None:
+            x64 = x
+        else:
+            r["rel_diff_vs_fp64_gpu_x"] = (torch.linalg.vector_norm(x - x64) / torch.linalg.vector_norm(x64)).item()
+        res[name] = r
+        log(f"{name}: {st['iters']} iters, {st['reliable_updates']} reliable, {dt * 1e3:.1f} ms, "
+            f"stencil {roof['achieved_gbs']:.0f} GB/s")
+    best = min(("f32", "f16"), key=lambda k: res[k]["time_to_solution_ms"])
+    return _common_out(args, res[best]["dw_gflops"], "GFLOP/s", res[best]["time_to_solution_ms"], best,
+                       {"workload": "24^3x48, U=exp(0.4iH), kappa=0.137, even-odd, mixed-precision CG "
+                                    "(FP32 or FP16 per-site-scaled inner, recon-12, FP64 reliable updates at 1e-2) "
+                                    "to true residual 1e-10", "lattice": list(L), "kappa": kappa, "best_inner": best},
+                       {"solves": res, "speedup_vs_plain_fp64": res["f64"]["time_to_solution_ms"] /
+                        res[best]["time_to_solution_ms"]})
+
+
+def bench_cfg4(args):
+    """16^3x32, 12 point sources per kappa in one batched solve (FP32 inner, FP64 outer)."""
+    import torch
+    import qcdgen
+    from paper_2409_03030_amd import wdirac as W
+    L, width, kappa0, U, b = make_workload("cfg2")
+    half = L[0] * L[1] * L[2] * L[3] // 2
+    Ud = torch.from_numpy(U).cuda()
+    B = torch.from_numpy(qcdgen.point_sources(L)).cuda()
+    lat = W.Lattice(L, BC)
+    for prec, recon in (("f64", 18), ("f32", 12)):
+        lat.set_gauge(Ud, prec, recon)
+        for nrhs in (1, 12):
+            sb, sw, sp = lat.autotune(prec, nrhs)
+            log(f"autotune {prec} nrhs {nrhs}: sites/block {sb}, swizzle {sw}, split {sp}")
+    p = W.default_params(inner="f32", delta=1e-2)
+    res = {}
+    tot_batched = tot_single = 0.0
+    flops = 0.0
+    for kappa in (0.130, 0.134, 0.1365):
+        lat.solve(B, [kappa] * 12, p)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            X, st = lat.solve(B, [kappa] * 12, p)
+        torch.cuda.synchronize()
+        tb = (time.perf_counter() - t0) / args.steps
+        t0 = time.perf_counter()
+        for r in range(12):
+            lat.solve(B[r].contiguous(), kappa, p)
+        torch.cuda.synchronize()
+        ts = time.perf_counter() - t0
+        its = [s["iters"] for s in st]
+        flops += sum(dw_flops(s, half) for s in st)
+        tot_batched += tb
+        tot_single += ts
+        res[str(kappa)] = {"batched_12rhs_ms": tb * 1e3, "sequential_12_single_ms": ts * 1e3,
+                           "speedup_batched": ts / tb, "iters_min": min(its), "iters_max": max(its),
+                           "all_converged": all(s["status"] == 0 for s in st),
+                           "max_true_resid": max(s["true_resid"] for s in st)}
+        log(f"kappa {kappa}: 12 rhs batched {tb * 1e3:.1f} ms vs sequential {ts * 1e3:.1f} ms, iters {min(its)}..{max(its)}")
+    roof = None
+    pt = W.SolveParams.from_buffer_copy(p)
+    pt.timing = 1
+    X, st = lat.solve(B, [0.1365] * 12, pt)
+    s0 = st[0]
+    roof = {"stencil_gbs": s0["hop_bytes"] / (s0["hop_ms"] * 1e-3) / 1e9,
+            "stencil_ms_avg": s0["hop_ms"] / max(1, s0["hop_launches"])}
+    return _common_out(args, flops / tot_batched / 1e9, "GFLOP/s", tot_batched / 3 * 1e3, "f32",
+                       {"workload": "16^3x32, 12 spin-colour point sources per kappa in one batched CG launch, "
+                                    "kappa in {0.130, 0.134, 0.1365}, complex64 inner / complex128 outer",
+                        "lattice": list(L), "nrhs": 12},
+                       {"per_kappa": res, "speedup_batched_vs_sequential": tot_single / tot_batched,
+                        "stencil_12rhs": roof})
+
+
+def bench_cfg5(args):
+    """Served stream: Poisson arrivals at 50/s over four lattice sizes, continuous batching."""
+    import threading
+    import numpy as np
+    import torch
+    import qcdgen
+    from paper_2409_03030_amd import wdirac as W
+    sizes = [(8, 8, 8, 8), (12, 12, 12, 24), (16, 16, 16, 32), (24, 24, 24, 48)]
+    g = qcdgen.rng(qcdgen.CONFIG_SEED_BASE + 4)
+    fields = []   # resident gauge fields: (lattice, width)
+    log("generating resident gauge fields ...")
+    for L in sizes:
+        for k in range(2 if L != (24, 24, 24, 48) else 1):
+            w = float(g.uniform(0.2, 0.5))
+            U = torch.from_numpy(qcdgen.links_exp(L, w, g)).cuda()
+            lat = W.Lattice(L, BC)
+            for prec, recon in (("f64", 18), ("f32", 12), ("f16", 12)):
+                lat.set_gauge(U, prec, recon)
+            del U
+            fields.append((lat, w))
+    n_req = args.requests
+    rate = args.rate
+    arrivals = np.cumsum(g.exponential(1.0 / rate, n_req))
+    picks = [(fields[int(g.integers(0, len(fields)))], float(g.uniform(0.12, 0.136))) for _ in range(n_req)]
+    sources = {}
+    for (lat, _), _k in picks:
+        if lat.L not in sources:
+            sources[lat.L] = [torch.from_numpy(qcdgen.gaussian_spinor(lat.L, g)).cuda() for _ in range(4)]
+    torch.cuda.synchronize()
+
+    def run(params, label):
+        free, total = torch.cuda.mem_get_info()
+        pool = int(min(24 << 30, free * 0.5))
+        srv = W.Server(pool, max_slots=16, params=params)
+        lat_s = []
+        done = {}
+        t_start = time.perf_counter()
+        tickets = []
+
+        def submit_all():
+            for i in range(n_req):
+                (lat, w), kappa = picks[i]
+                while time.perf_counter() - t_start < arrivals[i]:
+                    time.sleep(0.0002)
+                b = sources[lat.L][i % 4]
+                t = srv.submit(lat, b, kappa)
+                tickets.append((t, i, time.perf_counter() - t_start))
+        th = threading.Thread(target=submit_all)
+        th.start()
+        pending = {}
+        k = 0
+        while len(done) < n_req:
+            while k < len(tickets):
+                t, i, ts = tickets[k]
+                pending[t] = (i, ts)
+                k += 1
+            for t in list(pending):
+                r = srv.poll(t)
+                if r is not None:
+                    i, ts = pending.pop(t)
+                    x, st = r
+                    done[i] = (ts, time.perf_counter() - t_start, st[0])
+            time.sleep(0.0005)
+        th.join()
+        t_end = max(v[1] for v in done.values())
+        srv.close()
+        lat_ms = np.array([(v[1] - arrivals[i]) * 1e3 for i, v in done.items()])
+        ok = all(v[2]["status"] == 0 for v in done.values())
+        resid = max(v[2]["true_resid"] for v in done.values())
+        out = {"requests": n_req, "offered_rate_per_s": rate, "p50_ms": float(np.percentile(lat_ms, 50)),
+               "p99_ms": float(np.percentile(lat_ms, 99)), "mean_ms": float(lat_ms.mean()),
+               "solves_per_s": n_req / t_end, "all_converged": ok, "max_true_resid": resid,
+               "wall_s": t_end}
+        log(f"{label}: p50 {out['p50_ms']:.1f} ms, p99 {out['p99_ms']:.1f} ms, {out['solves_per_s']:.1f} solves/s")
+        return out
+
+    mixed = run(W.default_params(inner="f16", delta=1e-2), "served, FP16 inner")
+    mixed32 = run(W.default_params(inner="f32", delta=1e-2), "served, FP32 inner")
+    plain = run(W.default_params(), "served, plain FP64")
+    best = min((mixed, mixed32), key=lambda r: r["p99_ms"])
+    return _common_out(args, best["solves_per_s"], "solves/s", best["mean_ms"], "f16" if best is mixed else "f32",
+                       {"workload": f"served stream: Poisson arrivals at {rate}/s, lattices uniform over "
+                                    "{8^4, 12^3x24, 16^3x32, 24^3x48}, kappa U[0.12,0.136], link width U[0.2,0.5], "
+                                    "Gaussian sources, each to 1e-10, admission by HBM footprint",
+                        "requests": n_req},
+                       {"served_fp16_inner": mixed, "served_fp32_inner": mixed32, "served_plain_fp64": plain,
+                        "p99_ms": best["p99_ms"], "p50_ms": best["p50_ms"]})
+
+
+def bench_stencil(args):
+    """The stencil alone: n launches of the inner-iteration hop on a lattice, plus
+    a device copy of known size (the calibration reference for HBM counters)."""
+    import torch
+    import qcdgen
+    from paper_2409_03030_amd import wdirac as W
+    L = tuple(int(v) for v in args.lattice.split(","))
+    U = torch.from_numpy(qcdgen.links_exp(L, 0.4, qcdgen.rng(qcdgen.CONFIG_SEED_BASE + 2))).cuda()
+    lat = W.Lattice(L, BC)
+    half = L[0] * L[1] * L[2] * L[3] // 2
+    res = {}
+    for prec, recon in (("f64", 18), ("f64", 12), ("f32", 12), ("f16", 12)):
+        lat.set_gauge(U, prec, recon)
+        sb, sw, sp = lat.autotune(prec, 1)
+        ms = lat.time_hop(prec, 1, n=args.steps * 20)
+        link = {"f64": 16, "f32": 8, "f16": 4}[prec] * (9 if recon == 18 else 6)
+        sp_b = {"f64": 192, "f32": 96, "f16": 52}[prec]
+        nbytes = half * (8 * link + 2 * sp_b)
+        res[f"{prec}-{recon}"] = {"ms": ms, "bytes_per_launch": nbytes, "gbs": nbytes / (ms * 1e-3) / 1e9,
+                                  "gflops": FLOP_PER_SITE * half / (ms * 1e-3) / 1e9,
+                                  "shape": {"sites_per_block": sb, "swizzle": sw, "split": sp}}
+        log(f"stencil {prec}-{recon}: {ms * 1e3:.1f} us, {res[f'{prec}-{recon}']['gbs']:.0f} GB/s")
+    # calibration copy: 1 GiB read + 1 GiB written
+    a = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(5):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    cp = (time.perf_counter() - t0) / 5
+    res["copy_1GiB"] = {"ms": cp * 1e3, "gbs_read_plus_write": 2 * (1 << 30) / cp / 1e9}
+    best = res["f64-18"]
+    return _common_out(args, best["gbs"], "GB/s", best["ms"], "f64",
+                       {"workload": f"stencil only: one even-odd hop (V/2 output sites) on {'x'.join(map(str, L))}"},
+                       {"stencil": res})
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -231,6 +509,9 @@ def main():
     ap.add_argument("--workload", default="cfg2")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--requests", type=int, default=300, help="cfg5: number of served requests")
+    ap.add_argument("--rate", type=float, default=50.0, help="cfg5: Poisson arrival rate per second")
+    ap.add_argument("--lattice", default="24,24,24,48", help="stencil: lattice extents x,y,z,t")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU: this build has no multi-GPU path (asked for --gpus {args.gpus}).",
@@ -238,9 +519,12 @@ def main():
         sys.exit(2)
     if args.workload == "cfg2":
         bench_default(args)
-    else:
-        import bench_workloads  # noqa: F401  (other configurations)
-        bench_workloads.run(args)
+        return
+    fn = {"cfg1": bench_cfg1, "cfg3": bench_cfg3, "cfg4": bench_cfg4, "cfg5": bench_cfg5,
+          "stencil": bench_stencil}.get(args.workload)
+    if fn is None:
+        raise SystemExit(f"unknown workload {args.workload}")
+    print(json.dumps(fn(args)), flush=True)
 
 
 if __name__ == "__main__":

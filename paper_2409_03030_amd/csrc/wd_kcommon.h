@@ -225,30 +225,32 @@ __device__ void reduce_and_finalize(const Launch& L, const Slot& S, const Tile& 
   }
   __syncthreads();
   if (!is_last) return;
+  // Last block: the whole block gathers the partials, G groups of nr threads,
+  // group g summing blocks g, g+G, ... in order with 8 loads in flight, then
+  // a fixed-order tree over the groups.
+  const int T = (int)blockDim.x;
+  int G = 1;
+  while (2 * G * nr <= T) G *= 2;
   double acc = 0.0;
-  if (tid < nthr) {
-    for (int b = sl; b < S.nblk; b += sb) acc += load_partial(&S.partial[(size_t)b * nr + (tid % nr)]);
-  }
-  if (nr == 1) {
+  const int g = tid / nr;
+  if (g < G) {
+    const int r = tid - g * nr;
+    const double* part = S.partial + r;
+    int b = g;
+    for (; b + 7 * G < S.nblk; b += 8 * G) {
+      double q[8];
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
-    __syncthreads();
-    if ((tid & 63) == 0) lds[tid >> 6] = acc;
-    __syncthreads();
-    if (tid == 0) {
-      double s = 0.0;
-      const int nw = (nthr + 63) >> 6;
-      for (int w = 0; w < nw; ++w) s += lds[w];
-      if (S.st != nullptr) finalize_rhs(L.fin, S.st[0], s);
-      __hip_atomic_store(S.counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      for (int u = 0; u < 8; ++u) q[u] = load_partial(part + (size_t)(b + u * G) * nr);
+#pragma unroll
+      for (int u = 0; u < 8; ++u) acc += q[u];
     }
-    return;
+    for (; b < S.nblk; b += G) acc += load_partial(part + (size_t)b * nr);
   }
   __syncthreads();
-  if (tid < nthr) lds[tid] = acc;
+  if (g < G) lds[tid] = acc;
   __syncthreads();
-  for (int w = sb >> 1; w > 0; w >>= 1) {
-    if (sl < w) lds[tid] += lds[tid + w * nr];
+  for (int w = G >> 1; w > 0; w >>= 1) {
+    if (g < w) lds[tid] += lds[tid + w * nr];
     __syncthreads();
   }
   if (tid < nr && S.st != nullptr) finalize_rhs(L.fin, S.st[tid], lds[tid]);
