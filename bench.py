@@ -134,17 +134,28 @@ def bench_default(args):
     Ud = torch.from_numpy(U).to(dev)
     bd = torch.from_numpy(b).to(dev)
     lat = W.Lattice(L, BC)
-    lat.set_gauge(Ud, "f64", 18)
+    # plain FP64 CG with recon-18 and recon-12 FP64 links (both exact FP64
+    # arithmetic; recon-12 rebuilds the third row, error ~1e-16); the faster
+    # one is the headline
+    links = {}
+    for recon in (18, 12):
+        lat.set_gauge(Ud, "f64", recon)
+        sb, sw, sp = lat.autotune("f64", 1)
+        log(f"autotune f64-{recon}: sites/block {sb}, xcd swizzle {sw}, hop split {sp}")
+        ms = lat.time_hop("f64", 1, n=50)
+        links[recon] = ms
+    recon64 = min(links, key=links.get)
+    lat.set_gauge(Ud, "f64", recon64)
     lat.set_gauge(Ud, "f32", 12)
     lat.set_gauge(Ud, "f16", 12)
-    for prec in ("f64", "f32", "f16"):
+    for prec in ("f32", "f16"):
         sb, sw, sp = lat.autotune(prec, 1)
         log(f"autotune {prec}: sites/block {sb}, xcd swizzle {sw}, hop split {sp}")
     torch.cuda.synchronize()
 
     plain = W.default_params()  # EO, FP64 inner, tol 1e-10
-    log("timing plain FP64 CG ...")
-    x, st, dt = time_solves(lat, Ud, bd, kappa, plain, args.steps, args.warmup, set_gauge=[("f64", 18)])
+    log(f"timing plain FP64 CG (f64 links recon-{recon64}) ...")
+    x, st, dt = time_solves(lat, Ud, bd, kappa, plain, args.steps, args.warmup, set_gauge=[("f64", recon64)])
     if st["status"] != 0 or st["true_resid"] > 1e-10:
         raise SystemExit(f"plain CG failed: {st}")
     flops = dw_flops(st, half)
@@ -198,7 +209,7 @@ def bench_default(args):
             "boundary": "antiperiodic t",
             "precond": "even-odd",
             "inner": "f64",
-            "links": "f64 recon-18",
+            "links": f"f64 recon-{recon64}",
         },
         "time_to_solution_ms": dt * 1e3,
         "solves_per_s": 1.0 / dt,
@@ -212,7 +223,7 @@ def bench_default(args):
             "unit": "GB/s",
             "frac": roof["achieved_gbs"] / HBM_PEAK_GBS,
             "traffic": None,
-            "kernel": "hop_kernel<F64,18,*> (all stencil launches of one solve)",
+            "kernel": f"hop_kernel<F64,{recon64},*> (all stencil launches of one solve)",
             "avg_launch_ms": roof["hop_ms_avg"],
             "bytes_per_launch": roof["bytes_per_launch"],
             "stencil_gflops": roof["gflops"],

@@ -76,6 +76,15 @@ static void* role_ptr(const EItem* it, int role) {
   return nullptr;
 }
 
+static uint64_t fnv1a(uint64_t h, const void* data, size_t n) {
+  const unsigned char* c = (const unsigned char*)data;
+  for (size_t i = 0; i < n; ++i) {
+    h ^= c[i];
+    h *= 1099511628211ull;
+  }
+  return h;
+}
+
 struct Engine::Phase {
   bool hop;
   int prec;  // -1 = the inner precision
@@ -128,6 +137,14 @@ wd_status Engine::run_phase(const std::vector<EItem*>& list, const Phase& ph0) {
       sites += (long long)it->lat->g.n * (ph.parity == 2 ? 2 : 1) * nrhs;
     }
     finish_launch(L);
+    if (hash_) {
+      // key of a captured block: every launch's kernel choice and arguments
+      const int id[4] = {ph.hop ? 1 : 0, ph.prec, recon, ph.mode};
+      *hash_ = fnv1a(*hash_, id, sizeof id);
+      *hash_ = fnv1a(*hash_, &L, sizeof L);
+      i = j;
+      continue;
+    }
     if (ph.hop) {
       hipError_t e = timer_ ? timer_->begin(stream_) : hipSuccess;
       if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
@@ -218,48 +235,125 @@ wd_status Engine::export_item(EItem* it) {
   return WD_OK;
 }
 
-void Engine::choose_block() {
+int Engine::max_block() const {
   long long work = 0;
   for (auto* it : items) work += (long long)it->lat->g.n * it->nrhs * (eo_ ? 1 : 2);
   int K = p_.poll_every;
-  if (K <= 0) K = (int)std::max(2LL, std::min(32LL, (1LL << 21) / std::max(1LL, work)));
-  int ru = p_.delta > 0.0 ? std::min(K, 4) : K;
-  if (K % ru) K = (K / ru + 1) * ru;
-  K_ = K;
-  ru_every_ = ru;
+  if (K <= 0) K = (int)std::max(4LL, std::min(32LL, (1LL << 22) / std::max(1LL, work)));
+  return K;
 }
 
-void Engine::drop_graph() {
-  if (gexec_) (void)hipGraphExecDestroy(gexec_);
-  if (graph_) (void)hipGraphDestroy(graph_);
-  gexec_ = nullptr;
-  graph_ = nullptr;
+// Block sizes used for captured graphs: a small set keeps the cache small.
+static int round_block(int k, int kmax) {
+  static const int sizes[] = {1, 2, 3, 4, 6, 8, 12, 16, 24, 32, 48, 64};
+  int best = 1;
+  for (int s : sizes)
+    if (s <= k) best = s;
+  return std::min(best, kmax);
 }
 
-wd_status Engine::enqueue_direct() {
-  for (int j = 0; j < K_; ++j) {
+int BlockPlanner::next(const RhsState* hs, size_t n, int inflight, const int* idx) {
+  double best = 1e30;
+  bool any = false;
+  for (size_t j = 0; j < n; ++j) {
+    const size_t q = idx ? (size_t)idx[j] : j;
+    if (snap.size() <= q) snap.resize(q + 1, Snap{-1, 0.0});
+    const RhsState& s = hs[q];
+    if (s.state == ST_DONE || s.state == ST_NOTCONV || s.state == ST_NONFINITE) continue;
+    any = true;
+    if (s.state == ST_HOLD) {  // its update runs at the end of the block in flight
+      best = std::min(best, 1.0);
+      continue;
+    }
+    const double rho = s.iter_res2 > 0.0 ? s.iter_res2 : s.rho;
+    double target = s.stop2;
+    if (s.delta2 > 0.0) target = std::max(target, s.delta2 * s.max_rho);
+    double est = kmax;
+    if (snap[q].iters >= 0 && s.iters > snap[q].iters && snap[q].rho > 0.0 && rho > 0.0) {
+      const double rate = std::log(rho / snap[q].rho) / (s.iters - snap[q].iters);  // log decrease per iteration
+      if (rate < -1e-6) est = std::log(target / rho) / rate;
+    }
+    snap[q] = Snap{s.iters, rho};
+    est = std::max(0.0, est);
+    best = std::min(best, est);
+  }
+  if (!any) return 0;
+  const double left = best - inflight;  // iterations still needed after the blocks in flight
+  if (left < 0.5) return -1;             // the event falls in a block in flight: wait for it
+  return round_block((int)std::ceil(left), kmax);
+}
+
+int Engine::reliable_every() const { return 0; }
+
+// K inner iterations, then one reliable-update sequence: held rhs (converged
+// iterate, delta drop, or maxiter) get their FP64 true residual there.  The
+// host sizes K so that a block ends where the next such event is expected.
+wd_status Engine::enqueue_direct(int K) {
+  for (int j = 0; j < K; ++j) {
     wd_status s = run_iteration();
     if (s != WD_OK) return s;
-    if ((j + 1) % ru_every_ == 0) {
-      s = run_reliable();
-      if (s != WD_OK) return s;
-    }
   }
-  return WD_OK;
+  return run_reliable();
 }
 
-wd_status Engine::enqueue_block() {
-  if (items.empty()) return WD_OK;
-  const bool use_graph = p_.use_graph && !timer_;
-  if (!use_graph) {
-    choose_block();
-    ++blocks;
-    return enqueue_direct();
+// Instantiated graphs, shared by every engine of the process and keyed by the
+// exact launches they contain, so repeated solves on the same buffers replay
+// without capturing again.  An entry is destroyed only after the last replay
+// recorded on it has completed.
+namespace {
+struct GraphEntry {
+  uint64_t key;
+  hipGraphExec_t exec;
+  hipEvent_t last;
+};
+std::mutex g_graph_mu;
+std::vector<GraphEntry> g_graphs;  // most recently used last
+constexpr size_t kGraphCap = 48;
+}  // namespace
+
+// A block is K copies of one iteration's launches plus one reliable-update
+// sequence, so its key is the hash of those launches and K.
+uint64_t Engine::block_key(int K) {
+  if (base_key_ == 0) {
+    uint64_t h = 1469598103934665603ull;
+    hash_ = &h;
+    (void)run_iteration();
+    (void)run_reliable();
+    hash_ = nullptr;
+    base_key_ = h | 1;
   }
-  if (!gexec_) {
-    choose_block();
+  return fnv1a(base_key_, &K, sizeof K);
+}
+
+wd_status Engine::enqueue_block(int K) {
+  if (items.empty()) return WD_OK;
+  const int ru = reliable_every();
+  if (K < 1) K = 1;
+  if (ru > 0 && K % ru) K = (K / ru + 1) * ru;
+  ++blocks;
+  if (!p_.use_graph || timer_) return enqueue_direct(K);
+  const uint64_t key = block_key(K);
+  std::lock_guard<std::mutex> lk(g_graph_mu);
+  GraphEntry ent{0, nullptr, nullptr};
+  for (size_t i = 0; i < g_graphs.size(); ++i)
+    if (g_graphs[i].key == key) {
+      ent = g_graphs[i];
+      g_graphs.erase(g_graphs.begin() + i);
+      break;
+    }
+  if (!ent.exec) {
+    // capture only blocks that repeat: the first use of a key launches
+    // directly (a changing set of served requests rarely repeats a block)
+    bool seen = false;
+    for (uint64_t k : seen_)
+      if (k == key) seen = true;
+    if (!seen) {
+      if (seen_.size() >= 256) seen_.erase(seen_.begin());
+      seen_.push_back(key);
+      return enqueue_direct(K);
+    }
     WD_HIP(hipStreamBeginCapture(stream_, hipStreamCaptureModeThreadLocal));
-    wd_status s = enqueue_direct();
+    wd_status s = enqueue_direct(K);
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamEndCapture(stream_, &g);
     if (s != WD_OK) {
@@ -267,15 +361,27 @@ wd_status Engine::enqueue_block() {
       return s;
     }
     if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
-    graph_ = g;
-    e = hipGraphInstantiate(&gexec_, graph_, nullptr, nullptr, 0);
+    e = hipGraphInstantiate(&ent.exec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
+    e = hipEventCreateWithFlags(&ent.last, hipEventDisableTiming);
     if (e != hipSuccess) {
-      drop_graph();
-      return hip_fail(e, "hipGraphInstantiate");
+      (void)hipGraphExecDestroy(ent.exec);
+      return hip_fail(e, "hipEventCreate");
     }
+    ent.key = key;
   }
-  ++blocks;
-  WD_HIP(hipGraphLaunch(gexec_, stream_));
+  hipError_t e = hipGraphLaunch(ent.exec, stream_);
+  if (e == hipSuccess) e = hipEventRecord(ent.last, stream_);
+  g_graphs.push_back(ent);
+  while (g_graphs.size() > kGraphCap) {
+    GraphEntry old = g_graphs.front();
+    g_graphs.erase(g_graphs.begin());
+    (void)hipEventSynchronize(old.last);
+    (void)hipGraphExecDestroy(old.exec);
+    (void)hipEventDestroy(old.last);
+  }
+  if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
   return WD_OK;
 }
 
@@ -345,32 +451,56 @@ wd_status run_batch(std::vector<EItem>& items, const wd_solve_params& p, RhsStat
       result = hip_fail(e, "poll buffers");
       break;
     }
-    // Two blocks in flight: while the GPU runs block k+1 the host reads the
-    // states copied after block k.  Finished rhs make later kernels no-ops.
-    auto post = [&](int k) -> wd_status {
-      wd_status s = eng.enqueue_block();
+    // Up to two blocks in flight: while the GPU runs one block the host reads
+    // the states copied after the previous one and sizes the next block so
+    // that it ends where the next reliable update or convergence is expected.
+    BlockPlanner plan;
+    plan.kmax = eng.max_block();
+    struct Posted {
+      int buf, K;
+    };
+    std::vector<Posted> fly;
+    int next_buf = 0;
+    auto post = [&](int K) -> wd_status {
+      wd_status s = eng.enqueue_block(K);
       if (s != WD_OK) return s;
+      const int k = next_buf;
+      next_buf ^= 1;
       hipError_t e2 = hipMemcpyAsync(hs[k], states, nst * sizeof(RhsState), hipMemcpyDeviceToHost, stream);
       if (e2 != hipSuccess) return hip_fail(e2, "state copy");
       e2 = hipEventRecord(ev[k], stream);
       if (e2 != hipSuccess) return hip_fail(e2, "hipEventRecord");
+      fly.push_back({k, K});
       return WD_OK;
     };
-    if ((result = post(0)) != WD_OK) break;
-    const long long block_cap = (long long)p.maxiter / 2 + 64;
-    int cur = 0;
+    const int k0 = std::min(plan.kmax, 8);
+    if ((result = post(k0)) != WD_OK) break;
+    if ((result = post(k0)) != WD_OK) break;
+    long long iters_posted = 2LL * k0;
     for (;;) {
-      if ((result = post(1 - cur)) != WD_OK) break;
-      e = hipEventSynchronize(ev[cur]);
+      const Posted done = fly.front();
+      fly.erase(fly.begin());
+      e = hipEventSynchronize(ev[done.buf]);
       if (e != hipSuccess) {
         result = hip_fail(e, "hipEventSynchronize");
         break;
       }
-      bool all = true;
-      for (size_t q = 0; q < nst; ++q) all = all && finished(hs[cur][q].state);
-      if (all) break;
-      if (eng.blocks > block_cap) break;  // the device caps iterations; this only bounds the host loop
-      cur = 1 - cur;
+      int inflight = 0;
+      for (auto& f : fly) inflight += f.K;
+      const int K = plan.next(hs[done.buf], nst, inflight);
+      if (K == 0) break;  // every rhs finished
+      if (iters_posted > (long long)p.maxiter + 64LL * plan.kmax) break;  // device caps iterations; bounds the host loop
+      if (K < 0) {
+        if (fly.empty() && (result = post(1)) != WD_OK) break;
+        continue;
+      }
+      if ((result = post(K)) != WD_OK) break;
+      iters_posted += K;
+      if (fly.size() < 2 && K >= plan.kmax) {
+        // far from any event: keep a second block queued so the GPU never waits
+        if ((result = post(K)) != WD_OK) break;
+        iters_posted += K;
+      }
     }
   } while (false);
   hipError_t es = hipStreamSynchronize(stream);

@@ -105,6 +105,7 @@ static void finish_item_locked(wd_server_s* S, EItem* it) {
 static void worker_main(wd_server_s* S) {
   (void)hipSetDevice(S->device);
   Engine eng(S->p, S->stream, S->states, nullptr);
+  BlockPlanner plan;
   const size_t nst = (size_t)S->max_slots * kMaxRhsPerRequest;
   RhsState* hs = nullptr;
   hipEvent_t ev = nullptr;
@@ -147,9 +148,25 @@ static void worker_main(wd_server_s* S) {
       if ((err = eng.start_item(it)) != WD_OK) break;
       eng.items.push_back(it);
       eng.set_changed();
+      for (int r = 0; r < it->nrhs; ++r) {  // a new occupant of the slot: forget the old history
+        const size_t q = (size_t)it->state_index + r;
+        if (plan.snap.size() <= q) plan.snap.resize(q + 1, BlockPlanner::Snap{-1, 0.0});
+        plan.snap[q] = BlockPlanner::Snap{-1, 0.0};
+      }
     }
     if (err != WD_OK) break;
-    if ((err = eng.enqueue_block()) != WD_OK) break;
+    // block size: up to the next expected event of any running request; new
+    // requests start with a short block so that their rate is known early
+    plan.kmax = eng.max_block();
+    int K = admitted.empty() ? plan.kmax : std::min(plan.kmax, 4);
+    if (admitted.empty() && !eng.items.empty()) {
+      std::vector<int> idx;
+      for (EItem* it : eng.items)
+        for (int r = 0; r < it->nrhs; ++r) idx.push_back(it->state_index + r);
+      const int k = plan.next(hs, idx.size(), 0, idx.data());
+      K = k > 0 ? k : 1;
+    }
+    if ((err = eng.enqueue_block(K)) != WD_OK) break;
     if (hipMemcpyAsync(hs, S->states, nst * sizeof(RhsState), hipMemcpyDeviceToHost, S->stream) != hipSuccess ||
         hipEventRecord(ev, S->stream) != hipSuccess || hipEventSynchronize(ev) != hipSuccess) {
       err = fail(WD_EDEVICE, "server: state poll failed");

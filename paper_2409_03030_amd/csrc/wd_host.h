@@ -115,15 +115,17 @@ class Engine {
  public:
   Engine(const wd_solve_params& p, hipStream_t s, RhsState* states, HopTimer* timer)
       : p_(p), eo_(p.precond == WD_EO), stream_(s), states_(states), timer_(timer) {}
-  ~Engine() { drop_graph(); }
   std::vector<EItem*> items;
   long long blocks = 0;  // poll blocks enqueued so far
 
   wd_status start_item(EItem* it);    // enqueue state init, source import, INIT
-  wd_status enqueue_block();          // K iterations with reliable updates
+  // Enqueue K inner iterations (K a multiple of reliable_every()), with a
+  // reliable-update sequence after every reliable_every() iterations.
+  wd_status enqueue_block(int K);
   wd_status export_item(EItem* it);   // x = x_h (boundary layout)
-  void set_changed() { drop_graph(); }
-  int iters_per_block() const { return K_; }
+  void set_changed() { base_key_ = 0; }
+  int max_block() const;              // block size for a cold start
+  int reliable_every() const;
   RhsState* states() const { return states_; }
 
  private:
@@ -131,17 +133,30 @@ class Engine {
   wd_status run_phase(const std::vector<EItem*>& list, const Phase& ph);
   wd_status run_iteration();
   wd_status run_reliable();
-  wd_status enqueue_direct();
-  void choose_block();
-  void drop_graph();
+  wd_status enqueue_direct(int K);
+  uint64_t block_key(int K);
   wd_solve_params p_;
   bool eo_;
   hipStream_t stream_;
   RhsState* states_;
   HopTimer* timer_;
-  int K_ = 8, ru_every_ = 8;
-  hipGraph_t graph_ = nullptr;
-  hipGraphExec_t gexec_ = nullptr;
+  uint64_t* hash_ = nullptr;          // when set, launches are hashed instead of issued
+  uint64_t base_key_ = 0;             // hash of one iteration + reliable sequence for the current items
+  std::vector<uint64_t> seen_;        // block keys launched once by this engine
+};
+
+// Sizes poll blocks from the residual history: the next block ends where the
+// earliest rhs is expected to reach its next event (delta drop or tolerance).
+struct BlockPlanner {
+  struct Snap {
+    int iters;
+    double rho;
+  };
+  std::vector<Snap> snap;
+  int kmax = 32;
+  // > 0: size of the next block; -1: wait for the blocks in flight; 0: all done.
+  // idx (optional) lists the state entries to consider; else entries 0..n-1.
+  int next(const RhsState* hs, size_t n, int inflight, const int* idx = nullptr);
 };
 
 // Fill stats from final device states (host copy).
