@@ -35,6 +35,92 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+# Sources that determine the stencil kernels' code; counter-derived traffic is
+# only reported while they are unchanged since the counters were taken.
+KERNEL_SOURCES = ["paper_2409_03030_amd/csrc/hop.hip", "paper_2409_03030_amd/csrc/wd_device.h",
+                  "paper_2409_03030_amd/csrc/wd_kcommon.h", "paper_2409_03030_amd/csrc/wd_launch.h"]
+TRAFFIC_DB = os.path.join(ROOT, "profiles", "traffic.json")
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def lookup_traffic(kernel, lattice):
+    """Counter-derived HBM bytes per launch of `kernel`, or None if not measured
+    for the current kernel sources."""
+    try:
+        db = json.load(open(TRAFFIC_DB))
+    except (OSError, ValueError):
+        return None
+    e = db.get(f"{kernel}|{lattice}")
+    if not e or e.get("source_hash") != kernel_source_hash():
+        return None
+    return e.get("bytes_per_launch")
+
+
+def summarize_pmc(fetch_csv, write_csv, kernel, lattice, out=TRAFFIC_DB):
+    """Fold two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE; KiB per dispatch)
+    into bytes per launch of `kernel`, scaled by what the same counters read for
+    the 1 GiB device copy in the same runs."""
+    import csv
+    import statistics
+
+    def per_kernel(path, counter):
+        vals, copy = [], []
+        for r in csv.DictReader(open(path)):
+            if r["Counter_Name"] != counter:
+                continue
+            v = float(r["Counter_Value"]) * 1024.0
+            if r["Kernel_Name"].startswith(kernel):
+                vals.append(v)
+            elif "copyBuffer" in r["Kernel_Name"] and int(r["Grid_Size"]) >= 131072:
+                copy.append(v)
+        return vals, copy
+
+    fv, fc = per_kernel(fetch_csv, "FETCH_SIZE")
+    wv, wc = per_kernel(write_csv, "WRITE_SIZE")
+    gib = float(1 << 30)
+    f_scale = gib / statistics.median(fc)
+    w_scale = gib / statistics.median(wc)
+    fetch = statistics.median(fv) * f_scale
+    write = statistics.median(wv) * w_scale
+    db = {}
+    if os.path.exists(out):
+        db = json.load(open(out))
+    db[f"{kernel}|{lattice}"] = {
+        "source_hash": kernel_source_hash(), "bytes_per_launch": fetch + write,
+        "fetch_bytes_per_launch": fetch, "write_bytes_per_launch": write,
+        "dispatches": [len(fv), len(wv)], "copy_scale": {"FETCH_SIZE": f_scale, "WRITE_SIZE": w_scale},
+        "fetch_csv": fetch_csv, "write_csv": write_csv,
+    }
+    with open(out, "w") as fh:
+        json.dump(db, fh, indent=1, sort_keys=True)
+    return db[f"{kernel}|{lattice}"]
+
+
+def calibration_copy():
+    """A 1 GiB device-to-device copy: the known-size reference for the HBM counters."""
+    import torch
+    a = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / 3
+    del a, b
+    torch.cuda.empty_cache()
+    return 2.0 * (1 << 30) / dt / 1e9
+
+
 def dw_flops(stats, half_sites, eo=True):
     """Useful D_W flops of a solve: 1320 per stencil output site."""
     hops_per_iter = 4 if eo else 4  # EO: 4 half-lattice hops; FULL: 2 full-lattice = 4 half
@@ -82,7 +168,13 @@ def instrumented(lat, bd, kappa, params):
     x, st = lat.solve(bd, kappa, p)
     s = st[0]
     gbs = s["hop_bytes"] / (s["hop_ms"] * 1e-3) / 1e9
+    m = 2  # the fused CG residual stencil: r -= alpha (aux - c g5 H in), + |r|^2
+    n2 = max(1, s["hop_mode_launches"][m])
     return {
+        "cgr_launches": s["hop_mode_launches"][m],
+        "cgr_ms_avg": s["hop_mode_ms"][m] / n2,
+        "cgr_bytes_per_launch": s["hop_mode_bytes"][m] / n2,
+        "cgr_gbs": s["hop_mode_bytes"][m] / (s["hop_mode_ms"][m] * 1e-3) / 1e9 if s["hop_mode_ms"][m] > 0 else 0.0,
         "hop_ms_total": s["hop_ms"],
         "hop_launches": s["hop_launches"],
         "hop_ms_avg": s["hop_ms"] / max(1, s["hop_launches"]),
@@ -137,20 +229,28 @@ def bench_default(args):
     # plain FP64 CG with recon-18 and recon-12 FP64 links (both exact FP64
     # arithmetic; recon-12 rebuilds the third row, error ~1e-16); the faster
     # one is the headline
+    tuned = args.tune_file is not None
+    if tuned:
+        W.tune_import(open(args.tune_file).read())
     links = {}
     for recon in (18, 12):
         lat.set_gauge(Ud, "f64", recon)
-        sb, sw, sp = lat.autotune("f64", 1)
-        log(f"autotune f64-{recon}: sites/block {sb}, xcd swizzle {sw}, hop split {sp}")
-        ms = lat.time_hop("f64", 1, n=50)
-        links[recon] = ms
+        if not tuned:
+            sb, sw, sp = lat.autotune("f64", 1)
+            log(f"autotune f64-{recon}: sites/block {sb}, xcd swizzle {sw}, hop split {sp}")
+        links[recon] = lat.time_hop("f64", 1, n=50)
     recon64 = min(links, key=links.get)
     lat.set_gauge(Ud, "f64", recon64)
     lat.set_gauge(Ud, "f32", 12)
     lat.set_gauge(Ud, "f16", 12)
     for prec in ("f32", "f16"):
-        sb, sw, sp = lat.autotune(prec, 1)
-        log(f"autotune {prec}: sites/block {sb}, xcd swizzle {sw}, hop split {sp}")
+        if not tuned:
+            sb, sw, sp = lat.autotune(prec, 1)
+            log(f"autotune {prec}: sites/block {sb}, xcd swizzle {sw}, hop split {sp}")
+    if args.save_tune:
+        open(args.save_tune, "w").write(W.tune_export())
+    split64 = next(int(l.split()[9]) for l in W.tune_export().splitlines()
+                   if l.split()[:7] == [str(v) for v in (*L, 0, recon64, 1)])
     torch.cuda.synchronize()
 
     plain = W.default_params()  # EO, FP64 inner, tol 1e-10
@@ -182,6 +282,11 @@ def bench_default(args):
         }
         log(f"{inner} inner: {sm['iters']} iters, {dtm * 1e3:.2f} ms, stencil {rm['achieved_gbs']:.0f} GB/s")
 
+    kernel_name = f"void wd::hop_kernel<0, {recon64}, 2, {split64}>"
+    # the dominant kernel timed back to back (the same launch shape as in the CG)
+    cgr_ms = lat.time_hop("f64", 1, n=200, mode=2)
+    cgr_bytes = half * (8 * (16 * (9 if recon64 == 18 else 6)) + 4 * 192)
+    copy_gbs = calibration_copy()
     cpu = None
     if not args.no_cpu_baseline:
         log(f"timing the CPU oracle for ~{args.cpu_seconds:.0f} s ...")
@@ -218,16 +323,21 @@ def bench_default(args):
         "true_resid": st["true_resid"],
         "roofline": {
             "bound": "hbm",
-            "achieved": roof["achieved_gbs"],
+            "achieved": cgr_bytes / (cgr_ms * 1e-3) / 1e9,
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
-            "frac": roof["achieved_gbs"] / HBM_PEAK_GBS,
-            "traffic": None,
-            "kernel": f"hop_kernel<F64,{recon64},*> (all stencil launches of one solve)",
-            "avg_launch_ms": roof["hop_ms_avg"],
-            "bytes_per_launch": roof["bytes_per_launch"],
-            "stencil_gflops": roof["gflops"],
+            "frac": cgr_bytes / (cgr_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "traffic": lookup_traffic(kernel_name, "x".join(map(str, L))),
+            "kernel": kernel_name,
+            "avg_launch_ms": cgr_ms,
+            "bytes_per_launch": cgr_bytes,
+            "bytes_per_site": cgr_bytes / half,
+            "in_solve": {"avg_launch_ms": roof["cgr_ms_avg"], "launches": roof["cgr_launches"],
+                         "achieved_gbs": roof["cgr_gbs"], "note": "hipEvents around each launch of one solve"},
+            "all_stencil_launches": {"achieved_gbs": roof["achieved_gbs"], "avg_launch_ms": roof["hop_ms_avg"],
+                                     "launches": roof["hop_launches"], "gflops": roof["gflops"]},
         },
+        "copy_1GiB_gbs": copy_gbs,
         "mixed_precision": mixed,
         "cpu_baseline": cpu,
     }
@@ -523,7 +633,14 @@ def main():
     ap.add_argument("--requests", type=int, default=300, help="cfg5: number of served requests")
     ap.add_argument("--rate", type=float, default=50.0, help="cfg5: Poisson arrival rate per second")
     ap.add_argument("--lattice", default="24,24,24,48", help="stencil: lattice extents x,y,z,t")
+    ap.add_argument("--save-tune", default=None, help="write the tuning table to this file")
+    ap.add_argument("--tune-file", default=None, help="load this tuning table instead of autotuning")
+    ap.add_argument("--summarize-pmc", nargs=4, metavar=("FETCH_CSV", "WRITE_CSV", "KERNEL", "LATTICE"),
+                    help="fold two rocprofv3 --pmc runs into profiles/traffic.json and exit")
     args = ap.parse_args()
+    if args.summarize_pmc:
+        print(json.dumps(summarize_pmc(*args.summarize_pmc), indent=1))
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU: this build has no multi-GPU path (asked for --gpus {args.gpus}).",
               file=sys.stderr)

@@ -104,6 +104,11 @@ typedef struct {
   double hop_bytes;          /* algorithmic bytes of those launches: each launch reads its 8 links per
                                 output site once (shared by the rhs), its input spinor once per site and
                                 rhs, and reads/writes its epilogue vectors once */
+  /* the same three figures split by stencil epilogue: [0] plain H, [1] aux - c H
+     (with |.|^2), [2] CG residual update r -= alpha (aux - c g5 H), [3] FP64 true residual */
+  double hop_mode_ms[4];
+  int64_t hop_mode_launches[4];
+  double hop_mode_bytes[4];
 } wd_solve_stats;
 
 /* ---- lattice ---------------------------------------------------------- */
@@ -186,11 +191,14 @@ wd_status wd_solve_batch(int32_t nreq, const wd_solve_request* reqs, const wd_so
 
 /* ---- measurement and tuning ------------------------------------------ */
 
-/* Time n launches of the inner-iteration stencil (one even-odd hop, V/2 output
- * sites x nrhs, precision prec) with hipEvents on stream; *ms_per_launch gets
- * the mean duration.  Uses the tuned launch shape.  Needs
- * wd_apply_workspace_bytes(lat, prec, nrhs) of workspace.  Blocks the host. */
-wd_status wd_time_hop(wd_lattice lat, int32_t prec, int32_t nrhs, int32_t n,
+/* Time n back-to-back launches of one stencil kernel of the CG iteration (one
+ * even-odd hop, V/2 output sites x nrhs, precision prec, the tuned launch
+ * shape) with hipEvents on stream; *ms_per_launch gets the mean duration.
+ * mode selects the epilogue: 0 = plain H, 1 = aux - c H with |.|^2 reduction,
+ * 2 = the CG residual update r -= alpha (aux - c g5 H) with |r|^2 reduction.
+ * Operates on scratch data in the workspace (wd_apply_workspace_bytes(lat,
+ * prec, nrhs) bytes, zeroed first).  Blocks the host. */
+wd_status wd_time_hop(wd_lattice lat, int32_t prec, int32_t nrhs, int32_t mode, int32_t n,
                       void* ws, size_t ws_bytes, double* ms_per_launch, void* stream);
 
 /* Autotune the stencil launch shape (sites per workgroup, XCD-aware block

@@ -20,8 +20,8 @@ __global__ void __launch_bounds__(kBlock) blas_kernel(const Launch L) {
   using TA = typename RealOf<A>::T;
   const Tile t = make_tile(L);
   const Slot& S = L.s[t.slot];
-  // Launches with a reduction always run every block: the finalize step must
-  // see every rhs, also the ones this launch leaves untouched.
+  // Launches with a reduction run every block: every block partial of the
+  // slot must be written for the finalize step.
   if (L.fin == FIN_NONE && !slot_selected(L, S)) return;
   const bool both = L.parity == 2;
   const size_t pv = both ? (size_t)t.parity * S.vstride : 0;
@@ -103,7 +103,19 @@ __global__ void __launch_bounds__(kBlock) blas_kernel(const Launch L) {
       SpinorFmt<P>::store((char*)S.out + pv, ne, e, p);
     }
   }
-  if (L.fin != FIN_NONE) reduce_and_finalize(L, S, t, v);
+  if (L.fin != FIN_NONE) block_reduce_store(L, S, t, v);
+}
+
+// Stage 2 of a reduction: one block per slot (see gather_and_finalize).
+__global__ void __launch_bounds__(kBlock) finalize_kernel(const Launch L) {
+  const Slot& S = L.s[blockIdx.x];
+  gather_and_finalize(L, S, L.fin);
+}
+
+hipError_t launch_finalize(const Launch& L, hipStream_t stream) {
+  if (L.nslots <= 0 || L.fin == FIN_NONE) return hipSuccess;
+  hipLaunchKernelGGL(finalize_kernel, dim3((unsigned)L.nslots), dim3(kBlock), 0, stream, L);
+  return hipGetLastError();
 }
 
 template <int P>

@@ -40,8 +40,6 @@ ItemLayout item_layout(const wd_lattice_s* lat, const wd_solve_params& p, int nr
   size_t o = 0;
   l.off_partial = o;
   o += align_up((size_t)np * ((n + min_sblk(nrhs) - 1) / min_sblk(nrhs)) * nrhs * sizeof(double));
-  l.off_counter = o;
-  o += 256;
   l.off_bh = o; o += np * vh;
   l.off_xh = o; o += np * vh;
   l.off_rh = o; o += np * vh;
@@ -93,6 +91,8 @@ struct Engine::Phase {
   int g5in, g5out;
   int mask, fin;
   int in, out, aux;
+  int prefin;       // finalize of the previous phase's reduction, folded into this stencil launch
+  bool fin_folded;  // this phase's reduction is finished by the next phase (prefin)
 };
 
 wd_status Engine::run_phase(const std::vector<EItem*>& list, const Phase& ph0) {
@@ -112,6 +112,7 @@ wd_status Engine::run_phase(const std::vector<EItem*>& list, const Phase& ph0) {
     L.g5out = ph.g5out;
     L.mask = ph.mask;
     L.fin = ph.fin;
+    L.prefin = ph.prefin;
     L.nslots = (int)(j - i);
     long long sites = 0;
     for (size_t k = i; k < j; ++k) {
@@ -133,7 +134,6 @@ wd_status Engine::run_phase(const std::vector<EItem*>& list, const Phase& ph0) {
       S.hstride = l.hstride;
       S.st = it->st;
       S.partial = (double*)(it->base + l.off_partial);
-      S.counter = (unsigned*)(it->base + l.off_counter);
       sites += (long long)it->lat->g.n * (ph.parity == 2 ? 2 : 1) * nrhs;
     }
     finish_launch(L);
@@ -150,11 +150,16 @@ wd_status Engine::run_phase(const std::vector<EItem*>& list, const Phase& ph0) {
       if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
       e = launch_hop(L, ph.prec, recon, ph.mode, stream_);
       if (e != hipSuccess) return hip_fail(e, "stencil launch");
-      e = timer_ ? timer_->end(stream_, sites, hop_launch_bytes(ph.prec, recon, ph.mode, sites, nrhs)) : hipSuccess;
+      e = timer_ ? timer_->end(stream_, sites, hop_launch_bytes(ph.prec, recon, ph.mode, sites, nrhs), ph.mode)
+                 : hipSuccess;
       if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
     } else {
       hipError_t e = launch_blas(L, ph.prec, ph.mode, stream_);
       if (e != hipSuccess) return hip_fail(e, "vector kernel launch");
+    }
+    if (ph.fin != FIN_NONE && !ph.fin_folded) {
+      hipError_t e = launch_finalize(L, stream_);
+      if (e != hipSuccess) return hip_fail(e, "finalize launch");
     }
     i = j;
   }
@@ -162,17 +167,20 @@ wd_status Engine::run_phase(const std::vector<EItem*>& list, const Phase& ph0) {
 }
 
 wd_status Engine::run_iteration() {
+  // EO: the alpha reduction of the second stencil is finished by the first
+  // block of the third, which selects running rhs (alpha only changes the
+  // state of a running rhs when <p, A p> is not positive and finite).
   static const Phase eo[5] = {
-      {true, -1, HOP_PLAIN, 1, 0, 0, MASK_RUN, FIN_NONE, R_P, R_T1, R_NONE},
-      {true, -1, HOP_XPAY, 0, 0, 0, MASK_RUN, FIN_ALPHA, R_T1, R_T2, R_P},
-      {true, -1, HOP_PLAIN, 1, 1, 0, MASK_ACTIVE, FIN_NONE, R_T2, R_T1, R_NONE},
-      {true, -1, HOP_CGR, 0, 0, 1, MASK_ACTIVE, FIN_CG, R_T1, R_NONE, R_T2},
-      {false, -1, BLAS_CGUPD, 0, 0, 0, MASK_ACTIVE, FIN_NONE, R_NONE, R_P, R_NONE},
+      {true, -1, HOP_PLAIN, 1, 0, 0, MASK_RUN, FIN_NONE, R_P, R_T1, R_NONE, FIN_NONE, false},
+      {true, -1, HOP_XPAY, 0, 0, 0, MASK_RUN, FIN_ALPHA, R_T1, R_T2, R_P, FIN_NONE, true},
+      {true, -1, HOP_PLAIN, 1, 1, 0, MASK_RUN, FIN_NONE, R_T2, R_T1, R_NONE, FIN_ALPHA, false},
+      {true, -1, HOP_CGR, 0, 0, 1, MASK_ACTIVE, FIN_CG, R_T1, R_NONE, R_T2, FIN_NONE, false},
+      {false, -1, BLAS_CGUPD, 0, 0, 0, MASK_ACTIVE, FIN_NONE, R_NONE, R_P, R_NONE, FIN_NONE, false},
   };
   static const Phase full[3] = {
-      {true, -1, HOP_XPAY, 2, 0, 0, MASK_RUN, FIN_ALPHA, R_P, R_T2, R_P},
-      {true, -1, HOP_CGR, 2, 1, 1, MASK_ACTIVE, FIN_CG, R_T2, R_NONE, R_T2},
-      {false, -1, BLAS_CGUPD, 2, 0, 0, MASK_ACTIVE, FIN_NONE, R_NONE, R_P, R_NONE},
+      {true, -1, HOP_XPAY, 2, 0, 0, MASK_RUN, FIN_ALPHA, R_P, R_T2, R_P, FIN_NONE, false},
+      {true, -1, HOP_CGR, 2, 1, 1, MASK_ACTIVE, FIN_CG, R_T2, R_NONE, R_T2, FIN_NONE, false},
+      {false, -1, BLAS_CGUPD, 2, 0, 0, MASK_ACTIVE, FIN_NONE, R_NONE, R_P, R_NONE, FIN_NONE, false},
   };
   const Phase* k = eo_ ? eo : full;
   const int nk = eo_ ? 5 : 3;
@@ -185,18 +193,18 @@ wd_status Engine::run_iteration() {
 
 wd_status Engine::run_reliable() {
   static const Phase eo[6] = {
-      {false, -1, BLAS_RU_ACC, 0, 0, 0, MASK_HOLD, FIN_NONE, R_NONE, R_P, R_NONE},
-      {true, F64, HOP_PLAIN, 1, 0, 0, MASK_HOLD, FIN_NONE, R_XH, R_H1, R_NONE},
-      {true, F64, HOP_XPAY, 0, 0, 0, MASK_HOLD, FIN_NONE, R_H1, R_H2, R_XH},
-      {true, F64, HOP_PLAIN, 1, 1, 0, MASK_HOLD, FIN_NONE, R_H2, R_H1, R_NONE},
-      {true, F64, HOP_RESID, 0, 0, 1, MASK_HOLD, FIN_RESID, R_H1, R_NONE, R_H2},
-      {false, -1, BLAS_RU_FIN, 0, 0, 0, MASK_RU, FIN_NONE, R_NONE, R_P, R_NONE},
+      {false, -1, BLAS_RU_ACC, 0, 0, 0, MASK_HOLD, FIN_NONE, R_NONE, R_P, R_NONE, FIN_NONE, false},
+      {true, F64, HOP_PLAIN, 1, 0, 0, MASK_HOLD, FIN_NONE, R_XH, R_H1, R_NONE, FIN_NONE, false},
+      {true, F64, HOP_XPAY, 0, 0, 0, MASK_HOLD, FIN_NONE, R_H1, R_H2, R_XH, FIN_NONE, false},
+      {true, F64, HOP_PLAIN, 1, 1, 0, MASK_HOLD, FIN_NONE, R_H2, R_H1, R_NONE, FIN_NONE, false},
+      {true, F64, HOP_RESID, 0, 0, 1, MASK_HOLD, FIN_RESID, R_H1, R_NONE, R_H2, FIN_NONE, false},
+      {false, -1, BLAS_RU_FIN, 0, 0, 0, MASK_RU, FIN_NONE, R_NONE, R_P, R_NONE, FIN_NONE, false},
   };
   static const Phase full[4] = {
-      {false, -1, BLAS_RU_ACC, 2, 0, 0, MASK_HOLD, FIN_NONE, R_NONE, R_P, R_NONE},
-      {true, F64, HOP_XPAY, 2, 0, 0, MASK_HOLD, FIN_NONE, R_XH, R_H2, R_XH},
-      {true, F64, HOP_RESID, 2, 1, 1, MASK_HOLD, FIN_RESID, R_H2, R_NONE, R_H2},
-      {false, -1, BLAS_RU_FIN, 2, 0, 0, MASK_RU, FIN_NONE, R_NONE, R_P, R_NONE},
+      {false, -1, BLAS_RU_ACC, 2, 0, 0, MASK_HOLD, FIN_NONE, R_NONE, R_P, R_NONE, FIN_NONE, false},
+      {true, F64, HOP_XPAY, 2, 0, 0, MASK_HOLD, FIN_NONE, R_XH, R_H2, R_XH, FIN_NONE, false},
+      {true, F64, HOP_RESID, 2, 1, 1, MASK_HOLD, FIN_RESID, R_H2, R_NONE, R_H2, FIN_NONE, false},
+      {false, -1, BLAS_RU_FIN, 2, 0, 0, MASK_RU, FIN_NONE, R_NONE, R_P, R_NONE, FIN_NONE, false},
   };
   const Phase* k = eo_ ? eo : full;
   const int nk = eo_ ? 6 : 4;
@@ -220,10 +228,10 @@ wd_status Engine::start_item(EItem* it) {
     s.state = ST_RUN;
   }
   WD_HIP(hipMemcpyAsync(it->st, it->h_init.data(), it->nrhs * sizeof(RhsState), hipMemcpyHostToDevice, stream_));
-  WD_HIP(hipMemsetAsync(it->base + it->lay.off_counter, 0, 256, stream_));
   WD_HIP(launch_spinor_import(it->b, it->base + it->lay.off_bh, it->lay.hstride, it->lat->g, it->nrhs, eo_ ? 1 : 2,
                               F64, stream_));
-  const Phase init = {false, -1, BLAS_INIT, eo_ ? 0 : 2, 0, 0, MASK_NONE, FIN_INIT, R_NONE, R_P, R_NONE};
+  const Phase init = {false, -1, BLAS_INIT, eo_ ? 0 : 2, 0, 0, MASK_NONE, FIN_INIT, R_NONE, R_P, R_NONE, FIN_NONE,
+                      false};
   std::vector<EItem*> one{it};
   it->started_block = blocks;
   return run_phase(one, init);
@@ -526,10 +534,18 @@ wd_status run_batch(std::vector<EItem>& items, const wd_solve_params& p, RhsStat
     return result;
   }
   const double hop_ms = timer.on ? timer.total_ms() : 0.0;
+  double mms[4], mb[4];
+  long long mn[4];
+  timer.by_mode(mms, mn, mb);
   wd_status worst = WD_OK;
   for (size_t q = 0; q < nst; ++q) {
     wd_status st = stats_from_state(fin[q], secs, &timer, stats[q]);
     stats[q].hop_ms = hop_ms;
+    for (int m = 0; m < 4; ++m) {
+      stats[q].hop_mode_ms[m] = mms[m];
+      stats[q].hop_mode_launches[m] = mn[m];
+      stats[q].hop_mode_bytes[m] = mb[m];
+    }
     if (worst == WD_OK && st != WD_OK) worst = st;
   }
   timer.release();

@@ -26,8 +26,12 @@ __global__ void __launch_bounds__(kBlock) hop_kernel(const Launch L) {
   using TA = typename RealOf<A>::T;
   const Tile t = make_tile(L);
   const Slot& S = L.s[t.slot];
-  // Launches with a reduction always run every block: the finalize step must
-  // see every rhs, also the ones this launch leaves untouched.
+  // The previous launch's reduction is finished by the first block of each
+  // slot; this launch's own work must not depend on it (its mask reads only
+  // states that the finalize step leaves unchanged for the selected rhs).
+  if (L.prefin != FIN_NONE && t.lblk == 0) gather_and_finalize(L, S, L.prefin);
+  // Launches with a reduction run every block: every block partial of the
+  // slot must be written for the finalize step.
   if (L.fin == FIN_NONE && !slot_selected(L, S)) return;
   const bool both = L.parity == 2;
   const int par = t.parity;
@@ -113,7 +117,7 @@ __global__ void __launch_bounds__(kBlock) hop_kernel(const Launch L) {
       }
     }
   }
-  if (L.fin != FIN_NONE) reduce_and_finalize(L, S, t, v);
+  if (L.fin != FIN_NONE) block_reduce_store(L, S, t, v);
 }
 
 template <int P, int R, int MODE, int D>

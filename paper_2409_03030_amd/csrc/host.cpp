@@ -159,13 +159,31 @@ hipError_t HopTimer::begin(hipStream_t s) {
   return hipEventRecord(ev[used], s);
 }
 
-hipError_t HopTimer::end(hipStream_t s, long long sites, double b) {
+hipError_t HopTimer::end(hipStream_t s, long long sites, double b, int m) {
   if (!on) return hipSuccess;
   hipError_t r = hipEventRecord(ev[used + 1], s);
   used += 2;
   site_updates += sites;
   bytes += b;
+  mode.push_back(m);
+  mode_bytes.push_back(b);
   return r;
+}
+
+void HopTimer::by_mode(double ms[4], long long n[4], double b[4]) {
+  for (int m = 0; m < 4; ++m) {
+    ms[m] = 0.0;
+    n[m] = 0;
+    b[m] = 0.0;
+  }
+  for (size_t i = 0; i + 1 < used && i / 2 < mode.size(); i += 2) {
+    float t = 0.f;
+    if (hipEventElapsedTime(&t, ev[i], ev[i + 1]) != hipSuccess) continue;
+    const int m = mode[i / 2] & 3;
+    ms[m] += t;
+    n[m] += 1;
+    b[m] += mode_bytes[i / 2];
+  }
 }
 
 double hop_launch_bytes(int prec, int recon, int mode, long long sites, int nrhs) {
@@ -196,6 +214,8 @@ double HopTimer::total_ms() {
 void HopTimer::release() {
   for (auto e : ev) (void)hipEventDestroy(e);
   ev.clear();
+  mode.clear();
+  mode_bytes.clear();
   used = 0;
 }
 
@@ -294,9 +314,17 @@ wd_status wd_set_gauge(wd_lattice lat, const void* U, void* store, size_t store_
   return WD_OK;
 }
 
+// Four full-lattice vectors, then (for the timing calls) a scratch solver
+// state and block partials.
+static size_t timing_tail_bytes(const wd_lattice_s* lat, int nrhs) {
+  const size_t n = (size_t)lat->g.n;
+  return align_up((size_t)nrhs * sizeof(RhsState)) +
+         align_up(((n + min_sblk(nrhs) - 1) / min_sblk(nrhs)) * nrhs * sizeof(double));
+}
+
 size_t wd_apply_workspace_bytes(wd_lattice lat, int32_t prec, int32_t nrhs) {
   if (!lat || prec < F64 || prec > F16 || nrhs < 1) return 0;
-  return 4 * 2 * vec_bytes(prec, (size_t)lat->g.n, nrhs);
+  return 4 * 2 * vec_bytes(prec, (size_t)lat->g.n, nrhs) + timing_tail_bytes(lat, nrhs);
 }
 
 static wd_status apply_common(wd_lattice lat, void* y, const void* x, int32_t nrhs, double kappa, int32_t precond,
@@ -467,27 +495,37 @@ wd_status wd_solve_DdagD(wd_lattice lat, void* x, const void* b, int32_t nrhs, c
 // ---------------------------------------------------------------------------
 // measurement and tuning
 // ---------------------------------------------------------------------------
-static wd_status time_hop_shape(wd_lattice lat, int prec, int nrhs, int n, const Tune& t, char* ws, double* ms,
-                                hipStream_t st) {
+static wd_status time_hop_shape(wd_lattice lat, int prec, int nrhs, int mode, int n, const Tune& t, char* ws,
+                                double* ms, hipStream_t st) {
   const size_t vb = vec_bytes(prec, (size_t)lat->g.n, nrhs);
   const int recon = lat->store[prec].recon;
-  Launch L = base_launch(nrhs, t, 1);
+  Launch L = base_launch(nrhs, t, mode == HOP_PLAIN ? 1 : 0);
   L.nslots = 1;
   Slot& S = L.s[0];
-  fill_slot_geometry(S, lat, t.sblk, 1);
+  fill_slot_geometry(S, lat, t.sblk, L.parity);
   S.gauge = (const char*)lat->store[prec].ptr;
   S.in = ws;
   S.out = ws + 2 * vb;
+  S.aux = ws + 4 * vb;
+  S.r = ws + 6 * vb;
   S.vstride = vb;
+  S.astride = vec_bytes(acc_prec(prec), (size_t)lat->g.n, nrhs);
+  char* tail = ws + 8 * vb;
+  if (mode != HOP_PLAIN) {
+    L.fin = mode == HOP_XPAY ? FIN_ALPHA : FIN_CG;
+    L.mask = MASK_NONE;
+    S.st = (RhsState*)tail;
+    S.partial = (double*)(tail + align_up((size_t)nrhs * sizeof(RhsState)));
+  }
   finish_launch(L);
   hipEvent_t e0, e1;
   WD_HIP(hipEventCreate(&e0));
   WD_HIP(hipEventCreate(&e1));
   wd_status res = WD_OK;
   hipError_t e = hipSuccess;
-  for (int i = 0; i < 3 && e == hipSuccess; ++i) e = launch_hop(L, prec, recon, HOP_PLAIN, st);
+  for (int i = 0; i < 3 && e == hipSuccess; ++i) e = launch_hop(L, prec, recon, mode, st);
   if (e == hipSuccess) e = hipEventRecord(e0, st);
-  for (int i = 0; i < n && e == hipSuccess; ++i) e = launch_hop(L, prec, recon, HOP_PLAIN, st);
+  for (int i = 0; i < n && e == hipSuccess; ++i) e = launch_hop(L, prec, recon, mode, st);
   if (e == hipSuccess) e = hipEventRecord(e1, st);
   if (e == hipSuccess) e = hipEventSynchronize(e1);
   float f = 0.f;
@@ -499,15 +537,20 @@ static wd_status time_hop_shape(wd_lattice lat, int prec, int nrhs, int n, const
   return res;
 }
 
-wd_status wd_time_hop(wd_lattice lat, int32_t prec, int32_t nrhs, int32_t n, void* ws, size_t ws_bytes,
+wd_status wd_time_hop(wd_lattice lat, int32_t prec, int32_t nrhs, int32_t mode, int32_t n, void* ws, size_t ws_bytes,
                       double* ms_per_launch, void* stream) {
   wd_status s = check_lattice_for(lat, prec, WD_EO);
   if (s != WD_OK) return s;
   if (!ws || !ms_per_launch || n < 1) return fail(WD_EINVAL, "bad argument");
+  if (mode < HOP_PLAIN || mode > HOP_CGR) return fail(WD_EINVAL, "mode %d not timed (0, 1 or 2)", mode);
   if (nrhs < 1 || nrhs > kBlock / 2) return fail(WD_EINVAL, "nrhs out of range");
-  if (ws_bytes < wd_apply_workspace_bytes(lat, prec, nrhs)) return fail(WD_EBUFSIZE, "workspace too small");
+  const size_t need = wd_apply_workspace_bytes(lat, prec, nrhs);
+  if (ws_bytes < need) return fail(WD_EBUFSIZE, "workspace too small");
+  hipStream_t st = (hipStream_t)stream;
+  // zeroed scratch: finite inputs, zero solver state (alpha = c = 0)
+  WD_HIP(hipMemsetAsync(ws, 0, need, st));
   const Tune t = tune_lookup(lat, prec, lat->store[prec].recon, nrhs);
-  return time_hop_shape(lat, prec, nrhs, n, t, (char*)ws, ms_per_launch, (hipStream_t)stream);
+  return time_hop_shape(lat, prec, nrhs, mode, n, t, (char*)ws, ms_per_launch, st);
 }
 
 wd_status wd_autotune(wd_lattice lat, int32_t prec, int32_t nrhs, void* ws, size_t ws_bytes,
@@ -535,7 +578,7 @@ wd_status wd_autotune(wd_lattice lat, int32_t prec, int32_t nrhs, void* ws, size
         if (!valid_tune(t, nrhs)) continue;
         WD_HIP(hipMemsetAsync(w + 2 * vb, 0, vb, st));
         double ms = 0.0;
-        if ((s = time_hop_shape(lat, prec, nrhs, 20, t, w, &ms, st)) != WD_OK) return s;
+        if ((s = time_hop_shape(lat, prec, nrhs, HOP_PLAIN, 20, t, w, &ms, st)) != WD_OK) return s;
         // within one split the per-site arithmetic does not depend on the tiling:
         // every shape must produce the same bytes
         got.resize(vb);

@@ -68,9 +68,12 @@ struct HopTimer {
   size_t used = 0;
   long long site_updates = 0;
   double bytes = 0.0;
+  std::vector<int> mode;          // epilogue mode of each timed launch
+  std::vector<double> mode_bytes;  // its algorithmic bytes
   hipError_t begin(hipStream_t s);
-  hipError_t end(hipStream_t s, long long sites, double bytes);
+  hipError_t end(hipStream_t s, long long sites, double bytes, int mode);
   double total_ms();
+  void by_mode(double ms[4], long long n[4], double b[4]);
   void release();
 };
 
@@ -78,7 +81,7 @@ struct HopTimer {
 // item's base.  The per-rhs states live in a separate array shared by every
 // item of an engine so that one copy polls all of them.
 struct ItemLayout {
-  size_t off_partial, off_counter;
+  size_t off_partial;
   size_t off_bh, off_xh, off_rh, off_h1, off_h2;  // FP64 vectors
   size_t off_x, off_r;                            // accumulation precision
   size_t off_p, off_t1, off_t2;                   // inner precision

@@ -165,35 +165,27 @@ __device__ void finalize_rhs(int fin, RhsState& s, double sum) {
   }
 }
 
-// Block-level sum of v per rhs (tree over the block's sites, fixed order),
-// then the last arriving block of the slot sums the block partials in a
-// fixed order and runs finalize_rhs.  Deterministic: the result does not
-// depend on block scheduling.  All threads of the block must call this.
+// Two-stage FP64 reduction with a fixed summation order (deterministic:
+// independent of block scheduling).
 //
-// Cross-block visibility without fences: a release fence at device scope
-// writes back the whole L2 of the XCD, which costs more than the stencil
-// itself when every block does it.  Instead the partials are written with
-// device-scope atomic stores (coherent across the XCDs' L2s), the block
-// waits for them to complete before it counts itself in with a device-scope
-// atomic, and the last block reads the partials with device-scope atomic
-// loads.  The state it writes is read by later launches only.
-__device__ __forceinline__ void store_partial(double* p, double v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ double load_partial(const double* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-__device__ void reduce_and_finalize(const Launch& L, const Slot& S, const Tile& t, double v) {
+// Stage 1 (here, in the producing kernel): the block sums v per rhs (wave
+// butterfly shuffles for nrhs = 1, else a tree over the block's sites) and
+// writes its partial with an ordinary store.  Stage 2 runs in a separate
+// one-block-per-slot kernel (finalize_kernel) after the kernel boundary has
+// made every partial visible; it sums the partials in a fixed order and runs
+// the CG scalar update.  (Finishing inside the producer needs either a
+// device-scope release fence per block -- on gfx950 a write-back of the
+// XCD's whole L2 -- or coherent stores, waits and atomics whose round trips
+// serialise at the end of every block; both cost more than a small kernel.)
+// All threads of the block must call this.
+__device__ void block_reduce_store(const Launch& L, const Slot& S, const Tile& t, double v) {
   __shared__ double lds[kBlock];
-  __shared__ int is_last;
   const int tid = (int)threadIdx.x;
   const int nr = L.nrhs;
   const int sb = L.sblk;
   const int nthr = sb * nr;
   const int sl = tid / nr;
   if (nr == 1) {
-    // wave sums by butterfly shuffles, then the block's waves in order
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
     if ((tid & 63) == 0) lds[tid >> 6] = v;
@@ -202,32 +194,26 @@ __device__ void reduce_and_finalize(const Launch& L, const Slot& S, const Tile& 
       double s = 0.0;
       const int nw = (nthr + 63) >> 6;
       for (int w = 0; w < nw; ++w) s += lds[w];
-      lds[0] = s;
+      S.partial[t.lblk] = s;
     }
-    __syncthreads();
-  } else {
-    if (tid < nthr) lds[tid] = v;
-    __syncthreads();
-    for (int w = sb >> 1; w > 0; w >>= 1) {
-      if (sl < w) lds[tid] += lds[tid + w * nr];
-      __syncthreads();
-    }
+    return;
   }
-  if (tid < nr) store_partial(&S.partial[(size_t)t.lblk * nr + tid], lds[tid]);
-  // the partial stores must have completed before the arrival is counted
-  __atomic_signal_fence(__ATOMIC_SEQ_CST);
-  __builtin_amdgcn_s_waitcnt(0);
-  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  if (tid < nthr) lds[tid] = v;
   __syncthreads();
-  if (tid == 0) {
-    unsigned prev = __hip_atomic_fetch_add(S.counter, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    is_last = (prev == (unsigned)(S.nblk - 1));
+  for (int w = sb >> 1; w > 0; w >>= 1) {
+    if (sl < w) lds[tid] += lds[tid + w * nr];
+    __syncthreads();
   }
-  __syncthreads();
-  if (!is_last) return;
-  // Last block: the whole block gathers the partials, G groups of nr threads,
-  // group g summing blocks g, g+G, ... in order with 8 loads in flight, then
-  // a fixed-order tree over the groups.
+  if (tid < nr) S.partial[(size_t)t.lblk * nr + tid] = lds[tid];
+}
+
+// Stage 2: block b handles slot b.  G groups of nr threads, group g summing
+// partials g, g+G, ... in order with 8 loads in flight, then a fixed-order
+// tree over the groups, then finalize_rhs per rhs.
+__device__ void gather_and_finalize(const Launch& L, const Slot& S, int fin) {
+  __shared__ double lds[kBlock];
+  const int tid = (int)threadIdx.x;
+  const int nr = L.nrhs;
   const int T = (int)blockDim.x;
   int G = 1;
   while (2 * G * nr <= T) G *= 2;
@@ -240,21 +226,20 @@ __device__ void reduce_and_finalize(const Launch& L, const Slot& S, const Tile& 
     for (; b + 7 * G < S.nblk; b += 8 * G) {
       double q[8];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) q[u] = load_partial(part + (size_t)(b + u * G) * nr);
+      for (int u = 0; u < 8; ++u) q[u] = part[(size_t)(b + u * G) * nr];
 #pragma unroll
       for (int u = 0; u < 8; ++u) acc += q[u];
     }
-    for (; b < S.nblk; b += G) acc += load_partial(part + (size_t)b * nr);
+    for (; b < S.nblk; b += G) acc += part[(size_t)b * nr];
+    lds[tid] = acc;
   }
-  __syncthreads();
-  if (g < G) lds[tid] = acc;
   __syncthreads();
   for (int w = G >> 1; w > 0; w >>= 1) {
     if (g < w) lds[tid] += lds[tid + w * nr];
     __syncthreads();
   }
-  if (tid < nr && S.st != nullptr) finalize_rhs(L.fin, S.st[tid], lds[tid]);
-  if (tid == 0) __hip_atomic_store(S.counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (tid < nr && S.st != nullptr) finalize_rhs(fin, S.st[tid], lds[tid]);
+  __syncthreads();
 }
 
 }  // namespace wd

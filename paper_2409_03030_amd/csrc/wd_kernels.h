@@ -14,6 +14,10 @@ hipError_t launch_hop(const Launch& L, int prec, int recon, int mode, hipStream_
 // accumulation vectors x, r are F32 when prec is F16, else prec).
 hipError_t launch_blas(const Launch& L, int prec, int mode, hipStream_t stream);
 
+// Stage 2 of the reductions of a launch that had fin != FIN_NONE: one block
+// per slot sums the block partials and runs the CG scalar update.
+hipError_t launch_finalize(const Launch& L, hipStream_t stream);
+
 // complex128 boundary gauge field [mu][t][z][y][x][3][3] -> store.
 hipError_t launch_gauge_import(const void* U, void* store, const Geom& g, int prec, int recon,
                                hipStream_t stream);

@@ -62,7 +62,6 @@ struct Slot {
   size_t hstride;       // ... of an F64 vector
   RhsState* st;
   double* partial;      // [nblk][nrhs] block partial sums
-  unsigned* counter;    // arrival counter of the reduction
 };
 
 struct Launch {
@@ -75,6 +74,7 @@ struct Launch {
   int g5in, g5out;
   int mask;             // Mask
   int fin;              // Fin
+  int prefin;           // Fin of the previous launch's partials, run by block 0 of each slot before its own work
   int swz;              // 1: XCD-aware block order
   int total_blocks;
   double coef;          // epilogue coefficient when no RhsState is attached

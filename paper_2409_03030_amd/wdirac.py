@@ -59,10 +59,19 @@ class SolveStats(C.Structure):
         ("hop_launches", C.c_int64),
         ("hop_site_updates", C.c_int64),
         ("hop_bytes", C.c_double),
+        ("hop_mode_ms", C.c_double * 4),
+        ("hop_mode_launches", C.c_int64 * 4),
+        ("hop_mode_bytes", C.c_double * 4),
     ]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_ if k != "pad"}
+        d = {}
+        for k, _ in self._fields_:
+            if k == "pad":
+                continue
+            v = getattr(self, k)
+            d[k] = list(v) if hasattr(v, "__len__") else v
+        return d
 
 
 class SolveRequest(C.Structure):
@@ -93,7 +102,8 @@ _SIGS = [
     ("wd_batch_workspace_bytes", C.c_size_t, [C.c_int32, C.POINTER(SolveRequest), C.POINTER(SolveParams)]),
     ("wd_solve_batch", C.c_int32, [C.c_int32, C.POINTER(SolveRequest), C.POINTER(SolveParams), _P, C.c_size_t,
                                    C.POINTER(SolveStats), _P]),
-    ("wd_time_hop", C.c_int32, [_P, C.c_int32, C.c_int32, C.c_int32, _P, C.c_size_t, C.POINTER(C.c_double), _P]),
+    ("wd_time_hop", C.c_int32, [_P, C.c_int32, C.c_int32, C.c_int32, C.c_int32, _P, C.c_size_t,
+                                C.POINTER(C.c_double), _P]),
     ("wd_autotune", C.c_int32, [_P, C.c_int32, C.c_int32, _P, C.c_size_t, C.POINTER(C.c_int32),
                                 C.POINTER(C.c_int32), C.POINTER(C.c_int32), _P]),
     ("wd_tune_export", C.c_size_t, [C.c_char_p, C.c_size_t]),
@@ -279,12 +289,14 @@ class Lattice:
             _check(st, "wd_solve_DdagD")
         return x, [s.as_dict() for s in stats]
 
-    def time_hop(self, prec="f64", nrhs=1, n=50, stream=None):
+    def time_hop(self, prec="f64", nrhs=1, n=50, mode=0, stream=None):
+        """Mean duration (ms) of n back-to-back stencil launches; mode 0 plain,
+        1 with the aux - c H epilogue and reduction, 2 the fused CG residual update."""
         nb = int(lib().wd_apply_workspace_bytes(self.handle, PREC[prec], nrhs))
         dev = next(iter(self.stores.values())).device
         ws = self._workspace(nb, dev, ("apply", PREC[prec], nrhs))
         ms = C.c_double()
-        _check(lib().wd_time_hop(self.handle, PREC[prec], nrhs, n, _ptr(ws), ws.numel(), C.byref(ms),
+        _check(lib().wd_time_hop(self.handle, PREC[prec], nrhs, int(mode), n, _ptr(ws), ws.numel(), C.byref(ms),
                                  _stream(stream)), "wd_time_hop")
         return ms.value
 

@@ -221,3 +221,17 @@ def test_launch_shapes_match_oracle(nrhs, split, sblk, swz):
     x, st = lat.solve(_dev(b), 0.1365, W.default_params(inner="f16", delta=1e-2))
     assert st[0]["status"] == 0
     assert O.residual_DdagD(U, _host(x), b, 0.1365, BC, True) <= 1e-10
+
+
+def test_time_hop_modes():
+    """The stencil timer runs every timed epilogue on scratch data and rejects others."""
+    W = _W()
+    L = (8, 8, 8, 8)
+    lat = _lattice(L, qcdgen.links_unit(L), [("f64", 12), ("f16", 12)])
+    for prec in ("f64", "f16"):
+        for mode in (0, 1, 2):
+            ms = lat.time_hop(prec, 1, n=5, mode=mode)
+            assert 0.0 < ms < 10.0
+    with pytest.raises(W.WDError) as e:
+        lat.time_hop("f64", 1, n=5, mode=3)
+    assert e.value.status == W.WD_EINVAL
