@@ -87,6 +87,9 @@ typedef struct {
   int32_t poll_every;  /* iterations between host convergence polls; 0 = automatic */
   int32_t use_graph;   /* 1: replay captured hipGraphs of poll_every iterations */
   int32_t timing;      /* 1: time every stencil launch with hipEvents (disables graphs) */
+  int32_t rhs_group;   /* a request with more rhs is solved as consecutive groups of at most this
+                          many rhs, each its own slot of the same launches (smaller per-site working
+                          set in the L2); 0 = automatic (4) */
 } wd_solve_params;
 
 /* Per right-hand side result. */
@@ -155,7 +158,7 @@ wd_status wd_apply_DdagD(wd_lattice lat, void* y, const void* x, int32_t nrhs, d
 size_t wd_solver_workspace_bytes(wd_lattice lat, const wd_solve_params* params, int32_t nrhs);
 
 /* Fill *params with defaults: tol 1e-10, maxiter 100000, inner F64, recon 18,
- * delta 0, WD_EO, automatic polling, graphs on, timing off. */
+ * delta 0, WD_EO, automatic polling, graphs on, timing off, automatic rhs groups. */
 void wd_solve_params_default(wd_solve_params* params);
 
 /* Solve D^dag D x = b (WD_FULL) or D_hat^dag D_hat x_e = b_e (WD_EO) for nrhs

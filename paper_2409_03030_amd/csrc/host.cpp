@@ -230,6 +230,7 @@ wd_status check_params(const wd_solve_params& p) {
   if (!(p.delta >= 0.0 && p.delta < 1.0)) return fail(WD_EINVAL, "delta must be in [0, 1)");
   if (p.precond != WD_FULL && p.precond != WD_EO) return fail(WD_EINVAL, "precond %d unknown", p.precond);
   if (p.poll_every < 0 || p.poll_every > 4096) return fail(WD_EINVAL, "poll_every out of range");
+  if (p.rhs_group < 0 || p.rhs_group > kBlock / 2) return fail(WD_EINVAL, "rhs_group out of range");
   return WD_OK;
 }
 
@@ -412,6 +413,7 @@ void wd_solve_params_default(wd_solve_params* p) {
   p->poll_every = 0;
   p->use_graph = 1;
   p->timing = 0;
+  p->rhs_group = 0;
 }
 
 static wd_status check_item(wd_lattice lat, const wd_solve_params& p) {
@@ -425,7 +427,23 @@ static wd_status check_item(wd_lattice lat, const wd_solve_params& p) {
 
 size_t wd_solver_workspace_bytes(wd_lattice lat, const wd_solve_params* params, int32_t nrhs) {
   if (!lat || !params || nrhs < 1) return 0;
-  return states_bytes((size_t)nrhs) + item_layout(lat, *params, nrhs).total;
+  wd_solve_request r;
+  memset(&r, 0, sizeof r);
+  r.lat = lat;
+  r.nrhs = nrhs;
+  return wd_batch_workspace_bytes(1, &r, params);
+}
+
+// Groups of consecutive rhs of one request: (request, first rhs, count).
+struct RhsGroup {
+  int req, r0, n;
+};
+static std::vector<RhsGroup> rhs_groups(int32_t nreq, const wd_solve_request* reqs, const wd_solve_params& p) {
+  const int G = p.rhs_group > 0 ? p.rhs_group : 4;
+  std::vector<RhsGroup> out;
+  for (int i = 0; i < nreq; ++i)
+    for (int r0 = 0; r0 < reqs[i].nrhs; r0 += G) out.push_back({i, r0, std::min(G, reqs[i].nrhs - r0)});
+  return out;
 }
 
 size_t wd_batch_workspace_bytes(int32_t nreq, const wd_solve_request* reqs, const wd_solve_params* params) {
@@ -434,8 +452,8 @@ size_t wd_batch_workspace_bytes(int32_t nreq, const wd_solve_request* reqs, cons
   for (int i = 0; i < nreq; ++i) {
     if (!reqs[i].lat || reqs[i].nrhs < 1) return 0;
     nst += (size_t)reqs[i].nrhs;
-    tot += item_layout(reqs[i].lat, *params, reqs[i].nrhs).total;
   }
+  for (const RhsGroup& g : rhs_groups(nreq, reqs, *params)) tot += item_layout(reqs[g.req].lat, *params, g.n).total;
   return states_bytes(nst) + tot;
 }
 
@@ -460,14 +478,19 @@ wd_status wd_solve_batch(int32_t nreq, const wd_solve_request* reqs, const wd_so
   RhsState* states = (RhsState*)w;
   size_t off = states_bytes(nst);
   int si = 0;
-  std::vector<EItem> items((size_t)nreq);
-  for (int i = 0; i < nreq; ++i) {
-    EItem& it = items[i];
-    it.lat = reqs[i].lat;
-    it.x = reqs[i].x;
-    it.b = reqs[i].b;
-    it.nrhs = reqs[i].nrhs;
-    it.kappa.assign(reqs[i].kappa, reqs[i].kappa + it.nrhs);
+  const std::vector<RhsGroup> groups = rhs_groups(nreq, reqs, *params);
+  std::vector<EItem> items(groups.size());
+  for (size_t k = 0; k < groups.size(); ++k) {
+    const RhsGroup& gr = groups[k];
+    const wd_solve_request& rq = reqs[gr.req];
+    // field r of a request starts at r * V * 12 complex128 values
+    const size_t field = (size_t)2 * rq.lat->g.n * 12 * 16;
+    EItem& it = items[k];
+    it.lat = rq.lat;
+    it.x = (char*)rq.x + gr.r0 * field;
+    it.b = (const char*)rq.b + gr.r0 * field;
+    it.nrhs = gr.n;
+    it.kappa.assign(rq.kappa + gr.r0, rq.kappa + gr.r0 + gr.n);
     it.lay = item_layout(it.lat, *params, it.nrhs);
     it.base = w + off;
     off += it.lay.total;

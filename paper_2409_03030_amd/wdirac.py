@@ -43,6 +43,7 @@ class SolveParams(C.Structure):
         ("poll_every", C.c_int32),
         ("use_graph", C.c_int32),
         ("timing", C.c_int32),
+        ("rhs_group", C.c_int32),
     ]
 
 

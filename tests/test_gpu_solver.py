@@ -233,3 +233,65 @@ def test_config2_full_size_fp64_cg():
         xm = _host(xm)
         assert sm[0]["status"] == 0
         assert _oracle_resid(U, xm, b, 0.1365, eo=True) <= TOL
+
+
+def test_batch_mixed_nrhs_and_many_items():
+    """More items than slots per launch, and items with different nrhs in one batch."""
+    W = _W()
+    p = W.default_params(inner="f32", delta=1e-2)
+    reqs, host = [], []
+    for i in range(11):
+        L = [(4, 4, 4, 4), (4, 4, 2, 6), (6, 4, 4, 4)][i % 3]
+        g = qcdgen.rng(500 + i)
+        U = qcdgen.links_exp(L, 0.3, g)
+        nrhs = 1 if i % 4 else 3
+        b = qcdgen.gaussian_spinor(L, g, nrhs) if nrhs > 1 else qcdgen.gaussian_spinor(L, g)
+        kap = [0.12 + 0.001 * i] * nrhs
+        lat = _lattice(L, U, [("f64", 18), ("f32", 12)])
+        reqs.append((lat, _dev(b), kap))
+        host.append((U, b, kap))
+    res = W.solve_batch(reqs, p)
+    for (x, st), (U, b, kap) in zip(res, host):
+        x = _host(x)
+        if b.ndim == 6:
+            assert st[0]["status"] == 0
+            assert _oracle_resid(U, x, b, kap[0], eo=True) <= TOL
+        else:
+            for r in range(b.shape[0]):
+                assert st[r]["status"] == 0
+                assert _oracle_resid(U, x[r], b[r], kap[r], eo=True) <= TOL
+
+
+@pytest.mark.parametrize("inner", ["f32", "f16"])
+def test_full_mode_mixed_precision(inner):
+    L = (4, 4, 4, 8)
+    g = qcdgen.rng(601)
+    U = qcdgen.links_haar(L, g)
+    b = qcdgen.gaussian_spinor(L, g)
+    W = _W()
+    lat = _lattice(L, U, [("f64", 18), (inner, 12)])
+    x, st = lat.solve(_dev(b), 0.12, W.default_params(precond=W.FULL, inner=inner, delta=1e-2))
+    assert st[0]["status"] == 0
+    assert _oracle_resid(U, _host(x), b, 0.12, eo=False) <= TOL
+
+
+def test_server_multi_rhs_requests():
+    W = _W()
+    L = (8, 8, 4, 8)
+    g = qcdgen.rng(701)
+    U = qcdgen.links_exp(L, 0.3, g)
+    lat = _lattice(L, U, [("f64", 18), ("f32", 12)])
+    p = W.default_params(inner="f32", delta=1e-2)
+    srv = W.Server(1 << 30, max_slots=4, params=p)
+    B = qcdgen.point_sources(L)
+    b1 = qcdgen.gaussian_spinor(L, g)
+    t12 = srv.submit(lat, _dev(B), [0.13] * 12)
+    t1 = srv.submit(lat, _dev(b1), 0.125)
+    X, st12 = srv.wait(t12, 60000)
+    x1, st1 = srv.wait(t1, 60000)
+    srv.close()
+    X, x1 = _host(X), _host(x1)
+    for r in range(12):
+        assert st12[r]["status"] == 0
+        assert _oracle_resid(U, X[r], B[r], 0.13, eo=True) <= TOL
+    assert st1[0]["status"] == 0 and _oracle_resid(U, x1, b1, 0.125, eo=True) <= TOL
