@@ -146,7 +146,8 @@ template <> struct SpinorFmt<F16> {
 //   recon 18: all nine complexes; recon 12: rows 0 and 1, the third row is
 //   rebuilt as conj(row0 x row1), exact for SU(3).
 //   F64: double2 per complex.  F32-18: float2 per complex; F32-12: float4 per
-//   complex pair.  F16-18: half2 per complex; F16-12: 4 halves per pair.
+//   complex pair.  F16-18: half2 per complex; F16-12: 8 halves (complexes
+//   0..3) plus 4 halves (complexes 4..5).
 // ---------------------------------------------------------------------------
 template <int P, int R> struct LinkFmt;
 
@@ -243,31 +244,41 @@ union h4 {
   __half2 h[2];
 };
 
+// FP16-12: complexes 0..3 in one 16-byte chunk array, complexes 4..5 in one
+// 8-byte chunk array (two loads per link instead of three).
 template <> struct LinkFmt<F16, 12> {
-  static constexpr int chunks = 3;
+  static constexpr int chunks = 3;        // in 8-byte units: link_dir_bytes = 24 n
   static constexpr int chunk_bytes = 8;
   WD_HD static void load(const void* base, size_t n, size_t s, su3<float>& u) {
-    const uint2* v = (const uint2*)base;
+    const uint4* a = (const uint4*)base;
+    const uint2* b = (const uint2*)((const char*)base + 16 * n);
+    h8 d;
+    d.u = a[s];
+    h4 e;
+    e.u = b[s];
 #pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      h4 d;
-      d.u = v[k * n + s];
-      float2 a = __half22float2(d.h[0]);
-      float2 b = __half22float2(d.h[1]);
-      u.e[2 * k] = {a.x, a.y};
-      u.e[2 * k + 1] = {b.x, b.y};
+    for (int k = 0; k < 4; ++k) {
+      const float2 f = __half22float2(d.h[k]);
+      u.e[k] = {f.x, f.y};
+    }
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      const float2 f = __half22float2(e.h[k]);
+      u.e[4 + k] = {f.x, f.y};
     }
     reconstruct_row2(u);
   }
   WD_HD static void store(void* base, size_t n, size_t s, const su3<float>& u) {
-    uint2* v = (uint2*)base;
+    uint4* a = (uint4*)base;
+    uint2* b = (uint2*)((char*)base + 16 * n);
+    h8 d;
 #pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      h4 d;
-      d.h[0] = __floats2half2_rn(u.e[2 * k].re, u.e[2 * k].im);
-      d.h[1] = __floats2half2_rn(u.e[2 * k + 1].re, u.e[2 * k + 1].im);
-      v[k * n + s] = d.u;
-    }
+    for (int k = 0; k < 4; ++k) d.h[k] = __floats2half2_rn(u.e[k].re, u.e[k].im);
+    h4 e;
+#pragma unroll
+    for (int k = 0; k < 2; ++k) e.h[k] = __floats2half2_rn(u.e[4 + k].re, u.e[4 + k].im);
+    a[s] = d.u;
+    b[s] = e.u;
   }
 };
 
