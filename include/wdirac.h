@@ -216,7 +216,8 @@ wd_status wd_autotune(wd_lattice lat, int32_t prec, int32_t nrhs, void* ws, size
                       void* stream);
 
 /* Read or write the tuning table as text ("Lx Ly Lz Lt prec recon nrhs sblk swz split"
- * lines; split * sblk * nrhs <= 256, sblk * nrhs >= 64).
+ * lines; split in {1,2,4,8} (8 not at FP64); split * sblk * nrhs <= 256, or <= 512
+ * for split 8; sblk * nrhs >= 64).
  * wd_tune_export returns the bytes needed (including the NUL) and writes at
  * most cap bytes into buf (may be NULL). */
 size_t wd_tune_export(char* buf, size_t cap);

@@ -20,7 +20,7 @@ namespace wd {
 template <int P> struct AccOf { static constexpr int value = P == F16 ? F32 : P; };
 
 template <int P, int R, int MODE, int D>
-__global__ void __launch_bounds__(kBlock) hop_kernel(const Launch L) {
+__global__ void __launch_bounds__(D == 8 ? kMaxBlock : kBlock) hop_kernel(const Launch L) {
   using T = typename RealOf<P>::T;
   constexpr int A = AccOf<P>::value;
   using TA = typename RealOf<A>::T;
@@ -45,7 +45,7 @@ __global__ void __launch_bounds__(kBlock) hop_kernel(const Launch L) {
   }
   if (D > 1) {
     // parts 1..D-1 hand their sums to part 0, which adds them in part order
-    constexpr int kLds = D > 1 ? (D - 1) * 24 * (kBlock / D) : 1;
+    constexpr int kLds = D > 1 ? (D - 1) * 24 * ((D == 8 ? kMaxBlock : kBlock) / D) : 1;
     __shared__ T lds_acc[kLds];
     const int per = L.sblk * L.nrhs;
     const int loc = (int)threadIdx.x - t.part * per;
@@ -133,13 +133,16 @@ static hipError_t launch_split(const Launch& L, hipStream_t stream) {
     case 1: return launch_one<P, R, MODE, 1>(L, stream);
     case 2: return launch_one<P, R, MODE, 2>(L, stream);
     case 4: return launch_one<P, R, MODE, 4>(L, stream);
+    case 8:  // one hop per thread; its LDS combine would exceed 64 KB at FP64
+      if constexpr (P != F64) return launch_one<P, R, MODE, 8>(L, stream);
+      return hipErrorInvalidValue;
   }
   return hipErrorInvalidValue;
 }
 
 template <int P, int R>
 static hipError_t launch_mode(const Launch& L, int mode, hipStream_t stream) {
-  if (L.split * L.sblk * L.nrhs > kBlock) return hipErrorInvalidValue;
+  if (L.split * L.sblk * L.nrhs > (L.split == 8 ? kMaxBlock : kBlock)) return hipErrorInvalidValue;
   switch (mode) {
     case HOP_PLAIN: return launch_split<P, R, HOP_PLAIN>(L, stream);
     case HOP_XPAY: return launch_split<P, R, HOP_XPAY>(L, stream);

@@ -88,15 +88,17 @@ int default_sblk(int nrhs) {
   return s;
 }
 
-// A block holds split * sblk * nrhs threads (at most kBlock); a part of the
-// split covers whole waves; the reduction needs at least one full wave.
-bool valid_tune(const Tune& t, int nrhs) {
+// A block holds split * sblk * nrhs threads (at most kBlock, or kMaxBlock for
+// the 8-way split, which exists below FP64 only); a part of the split covers
+// whole waves; the reduction needs at least one full wave.
+bool valid_tune(const Tune& t, int nrhs, int prec) {
+  if (t.split == 8 && prec == F64) return false;
   const int sb = t.sblk;
   if (sb < 1 || (sb & (sb - 1)) != 0) return false;
-  if (t.split != 1 && t.split != 2 && t.split != 4) return false;
+  if (t.split != 1 && t.split != 2 && t.split != 4 && t.split != 8) return false;
   if (t.swz != 0 && t.swz != 1) return false;
   const int per = sb * nrhs;
-  if (per < 64 || t.split * per > kBlock) return false;
+  if (per < 64 || t.split * per > (t.split == 8 ? kMaxBlock : kBlock)) return false;
   if (t.split > 1 && per % 64 != 0) return false;
   return true;
 }
@@ -591,14 +593,14 @@ wd_status wd_autotune(wd_lattice lat, int32_t prec, int32_t nrhs, void* ws, size
   for (size_t i = 0; i < vb; ++i) pat[i] = (unsigned char)((i * 2654435761u) >> 13) & 0x3f;
   WD_HIP(hipMemcpyAsync(w, pat.data(), vb, hipMemcpyHostToDevice, st));
   WD_HIP(hipStreamSynchronize(st));
-  std::vector<unsigned char> ref[5], got;
+  std::vector<unsigned char> ref[9], got;
   double best = 1e30;
   Tune bt{default_sblk(nrhs), 1, 1};
-  for (int split = 1; split <= 4; split *= 2) {
-    for (int sblk = 1; sblk <= kBlock; sblk *= 2) {
+  for (int split = 1; split <= 8; split *= 2) {
+    for (int sblk = 1; sblk <= kMaxBlock; sblk *= 2) {
       for (int swz = 0; swz <= 1; ++swz) {
         Tune t{sblk, swz, split};
-        if (!valid_tune(t, nrhs)) continue;
+        if (!valid_tune(t, nrhs, prec)) continue;
         WD_HIP(hipMemsetAsync(w + 2 * vb, 0, vb, st));
         double ms = 0.0;
         if ((s = time_hop_shape(lat, prec, nrhs, HOP_PLAIN, 20, t, w, &ms, st)) != WD_OK) return s;
@@ -656,7 +658,7 @@ wd_status wd_tune_import(const char* text) {
     for (int i = 0; i < 10; ++i)
       if (!(ls >> v[i])) return fail(WD_EINVAL, "malformed tuning line '%s'", line.c_str());
     const Tune t{v[7], v[8], v[9]};
-    if (!valid_tune(t, v[6])) return fail(WD_EINVAL, "invalid tuning values in '%s'", line.c_str());
+    if (!valid_tune(t, v[6], v[4])) return fail(WD_EINVAL, "invalid tuning values in '%s'", line.c_str());
     rows.push_back({TuneKey(v[0], v[1], v[2], v[3], v[4], v[5], v[6]), t});
   }
   std::lock_guard<std::mutex> lk(g_tune_mu);

@@ -477,7 +477,8 @@ WD_HD void hop_mu(const Geom& g, const Coord& k, int parity, int s, int rhs, int
 }
 
 // The share `part` of the 8 hops when they are split over D threads:
-// D = 1 all directions, D = 2 (x,y) / (z,t), D = 4 one direction each.
+// D = 1 all directions, D = 2 (x,y) / (z,t), D = 4 one direction each,
+// D = 8 one hop each.
 template <int P, int R, int D>
 WD_HD void hop_part(const Geom& g, int parity, int s, int rhs, int nrhs, const char* gauge, const void* in,
                     const float bc[4], bool g5in, int part, spinor<typename RealOf<P>::T>& acc) {
@@ -496,12 +497,23 @@ WD_HD void hop_part(const Geom& g, int parity, int s, int rhs, int nrhs, const c
       hop_mu<P, R, 2>(g, k, parity, s, rhs, nrhs, gauge, in, bc, g5in, acc);
       hop_mu<P, R, 3>(g, k, parity, s, rhs, nrhs, gauge, in, bc, g5in, acc);
     }
-  } else {
+  } else if (D == 4) {
     switch (part) {
       case 0: hop_mu<P, R, 0>(g, k, parity, s, rhs, nrhs, gauge, in, bc, g5in, acc); break;
       case 1: hop_mu<P, R, 1>(g, k, parity, s, rhs, nrhs, gauge, in, bc, g5in, acc); break;
       case 2: hop_mu<P, R, 2>(g, k, parity, s, rhs, nrhs, gauge, in, bc, g5in, acc); break;
       default: hop_mu<P, R, 3>(g, k, parity, s, rhs, nrhs, gauge, in, bc, g5in, acc); break;
+    }
+  } else {
+    switch (part) {
+      case 0: hop_dir<P, R, 0, +1>(g, k, parity, s, rhs, nrhs, gauge, in, bc[0], g5in, acc); break;
+      case 1: hop_dir<P, R, 0, -1>(g, k, parity, s, rhs, nrhs, gauge, in, bc[0], g5in, acc); break;
+      case 2: hop_dir<P, R, 1, +1>(g, k, parity, s, rhs, nrhs, gauge, in, bc[1], g5in, acc); break;
+      case 3: hop_dir<P, R, 1, -1>(g, k, parity, s, rhs, nrhs, gauge, in, bc[1], g5in, acc); break;
+      case 4: hop_dir<P, R, 2, +1>(g, k, parity, s, rhs, nrhs, gauge, in, bc[2], g5in, acc); break;
+      case 5: hop_dir<P, R, 2, -1>(g, k, parity, s, rhs, nrhs, gauge, in, bc[2], g5in, acc); break;
+      case 6: hop_dir<P, R, 3, +1>(g, k, parity, s, rhs, nrhs, gauge, in, bc[3], g5in, acc); break;
+      default: hop_dir<P, R, 3, -1>(g, k, parity, s, rhs, nrhs, gauge, in, bc[3], g5in, acc); break;
     }
   }
 }

@@ -46,11 +46,11 @@ inline int acc_prec(int prec) { return prec == F16 ? F32 : prec; }
 double hop_launch_bytes(int prec, int recon, int mode, long long sites, int nrhs);
 
 struct Tune {
-  int sblk;   // sites per block (power of two, split * sblk * nrhs <= kBlock)
+  int sblk;   // sites per block (power of two; see valid_tune)
   int swz;    // XCD-aware block order
   int split;  // threads per (site, rhs) in the stencil: 1, 2 or 4
 };
-bool valid_tune(const Tune& t, int nrhs);
+bool valid_tune(const Tune& t, int nrhs, int prec);
 Tune tune_lookup(const wd_lattice_s* lat, int prec, int recon, int nrhs);
 void tune_store(const wd_lattice_s* lat, int prec, int recon, int nrhs, Tune t);
 int default_sblk(int nrhs);

@@ -179,7 +179,7 @@ __device__ void finalize_rhs(int fin, RhsState& s, double sum) {
 // serialise at the end of every block; both cost more than a small kernel.)
 // All threads of the block must call this.
 __device__ void block_reduce_store(const Launch& L, const Slot& S, const Tile& t, double v) {
-  __shared__ double lds[kBlock];
+  __shared__ double lds[kMaxBlock];
   const int tid = (int)threadIdx.x;
   const int nr = L.nrhs;
   const int sb = L.sblk;
@@ -211,7 +211,7 @@ __device__ void block_reduce_store(const Launch& L, const Slot& S, const Tile& t
 // partials g, g+G, ... in order with 8 loads in flight, then a fixed-order
 // tree over the groups, then finalize_rhs per rhs.
 __device__ void gather_and_finalize(const Launch& L, const Slot& S, int fin) {
-  __shared__ double lds[kBlock];
+  __shared__ double lds[kMaxBlock];
   const int tid = (int)threadIdx.x;
   const int nr = L.nrhs;
   const int T = (int)blockDim.x;

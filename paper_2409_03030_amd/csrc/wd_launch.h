@@ -15,7 +15,8 @@
 namespace wd {
 
 constexpr int kMaxSlots = 8;
-constexpr int kBlock = 256;  // upper bound on threads per block
+constexpr int kBlock = 256;     // threads per block, except the 8-way split stencil
+constexpr int kMaxBlock = 512;  // threads per block of the 8-way split stencil
 
 // Per right-hand-side solver state.  Lives in device memory; written by the
 // host before a solve and afterwards only by the last block of a reduction.
@@ -69,7 +70,7 @@ struct Launch {
   int nslots;
   int nrhs;
   int sblk;             // sites per block (power of two)
-  int split;            // threads per (site, rhs) in the stencil: 1, 2 or 4 (each takes 8/split hops)
+  int split;            // threads per (site, rhs) in the stencil: 1, 2, 4 or 8 (each takes 8/split hops)
   int parity;           // output parity 0 / 1, or 2 = both (input = the other one)
   int g5in, g5out;
   int mask;             // Mask

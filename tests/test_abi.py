@@ -94,6 +94,8 @@ def test_tuning_table_roundtrip():
     assert lib.wd_tune_import(b"16 16 16 32 0 18 1 3 1 1\n") == W.WD_EINVAL   # not a power of two
     assert lib.wd_tune_import(b"16 16 16 32 0 18 1 128 1 4\n") == W.WD_EINVAL  # 512 threads
     assert lib.wd_tune_import(b"16 16 16 32 0 18 1 64 1 3\n") == W.WD_EINVAL   # split 3
+    assert lib.wd_tune_import(b"16 16 16 32 1 12 1 64 1 8\n") == W.WD_OK       # 8-way split, FP32
+    assert lib.wd_tune_import(b"16 16 16 32 0 12 1 64 1 8\n") == W.WD_EINVAL   # not at FP64
 
 
 def test_status_strings():
