@@ -480,6 +480,22 @@ def bench_cfg4(args):
                            "all_converged": all(s["status"] == 0 for s in st),
                            "max_true_resid": max(s["true_resid"] for s in st)}
         log(f"kappa {kappa}: 12 rhs batched {tb * 1e3:.1f} ms vs sequential {ts * 1e3:.1f} ms, iters {min(its)}..{max(its)}")
+    # stress run: the 36 sources of the three kappas in one solve (kappa is per rhs)
+    B36 = torch.cat([B, B, B], 0).contiguous()
+    k36 = [0.130] * 12 + [0.134] * 12 + [0.1365] * 12
+    lat.solve(B36, k36, p)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        X36, st36 = lat.solve(B36, k36, p)
+    torch.cuda.synchronize()
+    t36 = (time.perf_counter() - t0) / args.steps
+    stress = {"ms": t36 * 1e3, "three_12rhs_batches_ms": tot_batched * 1e3,
+              "all_converged": all(s["status"] == 0 for s in st36),
+              "max_true_resid": max(s["true_resid"] for s in st36),
+              "iters_by_kappa": {str(k): [s["iters"] for s, kk in zip(st36, k36) if kk == k][:1][0]
+                                 for k in (0.130, 0.134, 0.1365)}}
+    log(f"36 rhs, mixed kappa, one solve: {t36 * 1e3:.1f} ms vs three 12-rhs solves {tot_batched * 1e3:.1f} ms")
     roof = None
     pt = W.SolveParams.from_buffer_copy(p)
     pt.timing = 1
@@ -492,7 +508,7 @@ def bench_cfg4(args):
                                     "kappa in {0.130, 0.134, 0.1365}, complex64 inner / complex128 outer",
                         "lattice": list(L), "nrhs": 12},
                        {"per_kappa": res, "speedup_batched_vs_sequential": tot_single / tot_batched,
-                        "stencil_12rhs": roof})
+                        "mixed_kappa_36rhs": stress, "stencil_12rhs": roof})
 
 
 def bench_cfg5(args):

@@ -10,7 +10,8 @@ namespace wd {
 template <int P> struct AccOfB { static constexpr int value = P == F16 ? F32 : P; };
 
 // BLAS_INIT  : x_h = 0, x = 0, r = low(b), p = low(b);   ||b||^2 -> FIN_INIT
-// BLAS_CGUPD : x += alpha p (active rhs); p = r + beta p (running rhs)
+// BLAS_CGUPD : x += alpha p (active rhs); p = r + beta p (running rhs); with
+//              prefin = FIN_CG every block first finishes the |r|^2 reduction
 // BLAS_RU_ACC: x_h += x, x = 0                            (held rhs)
 // BLAS_RU_FIN: r = low(r_h), p = r + beta p               (resumed rhs)
 template <int P, int MODE>
@@ -30,6 +31,48 @@ __global__ void __launch_bounds__(kBlock) blas_kernel(const Launch L) {
   const size_t ne = (size_t)S.g.n * L.nrhs;
   const size_t e = (size_t)t.site * L.nrhs + t.rhs;
   double v = 0.0;
+  if (MODE == BLAS_CGUPD) {
+    const bool on = t.valid && rhs_selected(S.st, L.mask, t.rhs);
+    spinor<T> p;
+    spinor<TA> x, r;
+    if (on) {  // issued before stage 2 so that both sets of loads are in flight together
+      SpinorFmt<P>::load((const char*)S.out + pv, ne, e, p);
+      SpinorFmt<A>::load((const char*)S.x + pa, ne, e, x);
+      SpinorFmt<A>::load((const char*)S.r + pa, ne, e, r);
+    }
+    __shared__ double s_beta[kBlock / 2];
+    __shared__ int s_state[kBlock / 2];
+    double beta_d;
+    int state;
+    if (L.prefin == FIN_CG) {
+      fold_finalize_cg(L, S, t, s_beta, s_state);
+      beta_d = s_beta[t.rhs];
+      state = s_state[t.rhs];
+    } else {
+      beta_d = S.st[t.rhs].beta;
+      state = S.st[t.rhs].state;
+    }
+    if (on) {
+      const TA alpha = (TA)S.st[t.rhs].alpha;
+#pragma unroll
+      for (int k = 0; k < 12; ++k) {
+        x.c[k].re += alpha * (TA)p.c[k].re;
+        x.c[k].im += alpha * (TA)p.c[k].im;
+      }
+      SpinorFmt<A>::store((char*)S.x + pa, ne, e, x);
+      if (state == ST_RUN) {
+        const TA beta = (TA)beta_d;
+        spinor<T> np;
+#pragma unroll
+        for (int k = 0; k < 12; ++k) {
+          np.c[k].re = (T)(r.c[k].re + beta * (TA)p.c[k].re);
+          np.c[k].im = (T)(r.c[k].im + beta * (TA)p.c[k].im);
+        }
+        SpinorFmt<P>::store((char*)S.out + pv, ne, e, np);
+      }
+    }
+    return;
+  }
   if (t.valid && rhs_selected(S.st, L.mask, t.rhs)) {
     if (MODE == BLAS_INIT) {
       spinor<double> b;
@@ -46,33 +89,6 @@ __global__ void __launch_bounds__(kBlock) blas_kernel(const Launch L) {
       spinor<T> pp;
       spinor_convert(pp, b);
       SpinorFmt<P>::store((char*)S.out + pv, ne, e, pp);
-    } else if (MODE == BLAS_CGUPD) {
-      const RhsState& st = S.st[t.rhs];
-      spinor<T> p;
-      SpinorFmt<P>::load((const char*)S.out + pv, ne, e, p);
-      {
-        const TA alpha = (TA)st.alpha;
-        spinor<TA> x;
-        SpinorFmt<A>::load((const char*)S.x + pa, ne, e, x);
-#pragma unroll
-        for (int k = 0; k < 12; ++k) {
-          x.c[k].re += alpha * (TA)p.c[k].re;
-          x.c[k].im += alpha * (TA)p.c[k].im;
-        }
-        SpinorFmt<A>::store((char*)S.x + pa, ne, e, x);
-      }
-      if (st.state == ST_RUN) {
-        const TA beta = (TA)st.beta;
-        spinor<TA> r;
-        SpinorFmt<A>::load((const char*)S.r + pa, ne, e, r);
-        spinor<T> np;
-#pragma unroll
-        for (int k = 0; k < 12; ++k) {
-          np.c[k].re = (T)(r.c[k].re + beta * (TA)p.c[k].re);
-          np.c[k].im = (T)(r.c[k].im + beta * (TA)p.c[k].im);
-        }
-        SpinorFmt<P>::store((char*)S.out + pv, ne, e, np);
-      }
     } else if (MODE == BLAS_RU_ACC) {
       spinor<double> xh;
       spinor<TA> x;

@@ -91,9 +91,21 @@ struct Engine::Phase {
   int g5in, g5out;
   int mask, fin;
   int in, out, aux;
-  int prefin;       // finalize of the previous phase's reduction, folded into this stencil launch
+  int prefin;       // finalize of the previous phase's reduction, folded into this launch
   bool fin_folded;  // this phase's reduction is finished by the next phase (prefin)
+  bool fold_small;  // FIN_CG producer / consumer pair: fold when every slot has few partials
 };
+
+// FIN_CG is finished by every block of the following vector kernel when each
+// slot has at most this many block partials (per launch: every block then
+// reads them all, so the fold only pays off while they are few).
+constexpr int kFoldPartials = 1024;
+
+static bool fold_ok(const Launch& L) {
+  for (int k = 0; k < L.nslots; ++k)
+    if ((long long)L.s[k].nblk * L.nrhs > kFoldPartials) return false;
+  return true;
+}
 
 wd_status Engine::run_phase(const std::vector<EItem*>& list, const Phase& ph0) {
   Phase ph = ph0;
@@ -137,6 +149,8 @@ wd_status Engine::run_phase(const std::vector<EItem*>& list, const Phase& ph0) {
       sites += (long long)it->lat->g.n * (ph.parity == 2 ? 2 : 1) * nrhs;
     }
     finish_launch(L);
+    const bool folded = ph.fold_small && fold_ok(L);
+    if (ph.fold_small && ph.prefin != FIN_NONE && !folded) L.prefin = FIN_NONE;
     if (hash_) {
       // key of a captured block: every launch's kernel choice and arguments
       const int id[4] = {ph.hop ? 1 : 0, ph.prec, recon, ph.mode};
@@ -157,7 +171,7 @@ wd_status Engine::run_phase(const std::vector<EItem*>& list, const Phase& ph0) {
       hipError_t e = launch_blas(L, ph.prec, ph.mode, stream_);
       if (e != hipSuccess) return hip_fail(e, "vector kernel launch");
     }
-    if (ph.fin != FIN_NONE && !ph.fin_folded) {
+    if (ph.fin != FIN_NONE && !ph.fin_folded && !folded) {
       hipError_t e = launch_finalize(L, stream_);
       if (e != hipSuccess) return hip_fail(e, "finalize launch");
     }
@@ -174,13 +188,13 @@ wd_status Engine::run_iteration() {
       {true, -1, HOP_PLAIN, 1, 0, 0, MASK_RUN, FIN_NONE, R_P, R_T1, R_NONE, FIN_NONE, false},
       {true, -1, HOP_XPAY, 0, 0, 0, MASK_RUN, FIN_ALPHA, R_T1, R_T2, R_P, FIN_NONE, true},
       {true, -1, HOP_PLAIN, 1, 1, 0, MASK_RUN, FIN_NONE, R_T2, R_T1, R_NONE, FIN_ALPHA, false},
-      {true, -1, HOP_CGR, 0, 0, 1, MASK_ACTIVE, FIN_CG, R_T1, R_NONE, R_T2, FIN_NONE, false},
-      {false, -1, BLAS_CGUPD, 0, 0, 0, MASK_ACTIVE, FIN_NONE, R_NONE, R_P, R_NONE, FIN_NONE, false},
+      {true, -1, HOP_CGR, 0, 0, 1, MASK_ACTIVE, FIN_CG, R_T1, R_NONE, R_T2, FIN_NONE, false, true},
+      {false, -1, BLAS_CGUPD, 0, 0, 0, MASK_ACTIVE, FIN_NONE, R_NONE, R_P, R_NONE, FIN_CG, false, true},
   };
   static const Phase full[3] = {
       {true, -1, HOP_XPAY, 2, 0, 0, MASK_RUN, FIN_ALPHA, R_P, R_T2, R_P, FIN_NONE, false},
-      {true, -1, HOP_CGR, 2, 1, 1, MASK_ACTIVE, FIN_CG, R_T2, R_NONE, R_T2, FIN_NONE, false},
-      {false, -1, BLAS_CGUPD, 2, 0, 0, MASK_ACTIVE, FIN_NONE, R_NONE, R_P, R_NONE, FIN_NONE, false},
+      {true, -1, HOP_CGR, 2, 1, 1, MASK_ACTIVE, FIN_CG, R_T2, R_NONE, R_T2, FIN_NONE, false, true},
+      {false, -1, BLAS_CGUPD, 2, 0, 0, MASK_ACTIVE, FIN_NONE, R_NONE, R_P, R_NONE, FIN_CG, false, true},
   };
   const Phase* k = eo_ ? eo : full;
   const int nk = eo_ ? 5 : 3;

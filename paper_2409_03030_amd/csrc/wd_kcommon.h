@@ -107,6 +107,8 @@ __device__ void finalize_rhs(int fin, RhsState& s, double sum) {
         if (finite_d(sum) && sum > 0.0) {
           s.alpha = s.rho / sum;
           s.active = 1;
+          s.iters += 1;
+          s.rho_prev = s.rho;
         } else {
           s.alpha = 0.0;
           s.active = 0;
@@ -119,19 +121,21 @@ __device__ void finalize_rhs(int fin, RhsState& s, double sum) {
       break;
     }
     case FIN_CG: {  // sum = ||r_new||^2
+      // Reads only fields that it leaves unchanged (active, rho_prev, iters,
+      // the limits) or changes idempotently (max_rho), so running it again
+      // on its own output gives the same state: every block of the next
+      // vector kernel may run it while the first block stores the result.
       if (s.active) {
-        s.iters += 1;
         s.iter_res2 = sum;
         if (!finite_d(sum)) {
           s.state = ST_NONFINITE;
           s.beta = 0.0;
           break;
         }
-        s.beta = sum / s.rho;
-        s.rho_prev = s.rho;
+        s.beta = sum / s.rho_prev;
         s.rho = sum;
         if (sum > s.max_rho) s.max_rho = sum;
-        if (sum <= s.stop2 || sum <= s.delta2 * s.max_rho || s.iters >= s.maxiter) s.state = ST_HOLD;
+        s.state = (sum <= s.stop2 || sum <= s.delta2 * s.max_rho || s.iters >= s.maxiter) ? ST_HOLD : ST_RUN;
       }
       break;
     }
@@ -170,10 +174,12 @@ __device__ void finalize_rhs(int fin, RhsState& s, double sum) {
 //
 // Stage 1 (here, in the producing kernel): the block sums v per rhs (wave
 // butterfly shuffles for nrhs = 1, else a tree over the block's sites) and
-// writes its partial with an ordinary store.  Stage 2 runs in a separate
-// one-block-per-slot kernel (finalize_kernel) after the kernel boundary has
-// made every partial visible; it sums the partials in a fixed order and runs
-// the CG scalar update.  (Finishing inside the producer needs either a
+// writes its partial with an ordinary store.  Stage 2 runs after the kernel
+// boundary has made every partial visible: in a separate one-block-per-slot
+// kernel (finalize_kernel), in the first block of the next stencil, or (for
+// FIN_CG with few partials) in every block of the next vector kernel; it
+// sums the partials in a fixed order and runs the CG scalar update.
+// (Finishing inside the producer needs either a
 // device-scope release fence per block -- on gfx950 a write-back of the
 // XCD's whole L2 -- or coherent stores, waits and atomics whose round trips
 // serialise at the end of every block; both cost more than a small kernel.)
@@ -207,38 +213,86 @@ __device__ void block_reduce_store(const Launch& L, const Slot& S, const Tile& t
   if (tid < nr) S.partial[(size_t)t.lblk * nr + tid] = lds[tid];
 }
 
-// Stage 2: block b handles slot b.  G groups of nr threads, group g summing
-// partials g, g+G, ... in order with 8 loads in flight, then a fixed-order
-// tree over the groups, then finalize_rhs per rhs.
-__device__ void gather_and_finalize(const Launch& L, const Slot& S, int fin) {
-  __shared__ double lds[kMaxBlock];
-  const int tid = (int)threadIdx.x;
-  const int nr = L.nrhs;
-  const int T = (int)blockDim.x;
+// Stage 2 summation order, fixed by nrhs alone so that every kernel that
+// runs stage 2 (whatever its block size) gets bitwise the same sums: for
+// each rhs, G groups (G = the largest power of two with G * nrhs <= 256);
+// group g sums partials g, g+G, g+2G, ... in increasing order, then a
+// pairwise tree combines the groups.  Threads take several groups when the
+// block has fewer than G * nrhs threads.  On return red[g * nr + r] holds
+// nothing useful except red[r] = the sum for rhs r.  All threads of the
+// block must call this.
+constexpr int kRedSlots = 256;
+
+__device__ __forceinline__ int red_groups(int nr) {
   int G = 1;
-  while (2 * G * nr <= T) G *= 2;
-  double acc = 0.0;
-  const int g = tid / nr;
-  if (g < G) {
-    const int r = tid - g * nr;
-    const double* part = S.partial + r;
-    int b = g;
-    for (; b + 7 * G < S.nblk; b += 8 * G) {
-      double q[8];
+  while (2 * G * nr <= kRedSlots) G *= 2;
+  return G;
+}
+
+__device__ void reduce_partials(const double* __restrict__ part, int npart, int nr, double* red) {
+  const int tid = (int)threadIdx.x;
+  const int G = red_groups(nr);
+  const int per = (int)blockDim.x / nr;  // groups worked on at once, per rhs
+  const int r = tid % nr;
+  const bool on = tid < per * nr;
+  if (on) {
+    for (int g = tid / nr; g < G; g += per) {
+      const double* q0 = part + r;
+      double acc = 0.0;
+      int b = g;
+      for (; b + 7 * G < npart; b += 8 * G) {
+        double q[8];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) q[u] = part[(size_t)(b + u * G) * nr];
+        for (int u = 0; u < 8; ++u) q[u] = q0[(size_t)(b + u * G) * nr];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) acc += q[u];
+        for (int u = 0; u < 8; ++u) acc += q[u];
+      }
+      for (; b < npart; b += G) acc += q0[(size_t)b * nr];
+      red[g * nr + r] = acc;
     }
-    for (; b < S.nblk; b += G) acc += part[(size_t)b * nr];
-    lds[tid] = acc;
   }
   __syncthreads();
   for (int w = G >> 1; w > 0; w >>= 1) {
-    if (g < w) lds[tid] += lds[tid + w * nr];
+    if (on)
+      for (int g = tid / nr; g < w; g += per) red[g * nr + r] += red[(g + w) * nr + r];
     __syncthreads();
   }
-  if (tid < nr && S.st != nullptr) finalize_rhs(fin, S.st[tid], lds[tid]);
+}
+
+// Stage 2 in its own kernel (block b handles slot b) or in the first block of
+// the next stencil: sum the partials and run the CG scalar update.
+__device__ void gather_and_finalize(const Launch& L, const Slot& S, int fin) {
+  __shared__ double red[kRedSlots];
+  reduce_partials(S.partial, S.nblk, L.nrhs, red);
+  const int tid = (int)threadIdx.x;
+  if (tid < L.nrhs && S.st != nullptr) finalize_rhs(fin, S.st[tid], red[tid]);
+  __syncthreads();
+}
+
+// Stage 2 of FIN_CG run by every block of the vector kernel that follows the
+// reducing stencil: each block sums the same partials in the same order and
+// applies FIN_CG to a private copy of the states, handing beta and the new
+// state to its threads; the first block of the slot also stores the states.
+// Sound because FIN_CG is idempotent (see finalize_rhs): a block that reads
+// a state after the first block stored it computes the same result.
+__device__ void fold_finalize_cg(const Launch& L, const Slot& S, const Tile& t, double* beta, int* state) {
+  __shared__ double red[kRedSlots];
+  reduce_partials(S.partial, S.nblk, L.nrhs, red);
+  const int tid = (int)threadIdx.x;
+  if (tid < L.nrhs) {
+    RhsState s = S.st[tid];
+    finalize_rhs(FIN_CG, s, red[tid]);
+    beta[tid] = s.beta;
+    state[tid] = s.state;
+    if (t.lblk == 0 && s.active) {
+      RhsState& d = S.st[tid];
+      d.iter_res2 = s.iter_res2;
+      d.beta = s.beta;
+      d.rho = s.rho;
+      d.max_rho = s.max_rho;
+      d.state = s.state;
+    }
+  }
   __syncthreads();
 }
 

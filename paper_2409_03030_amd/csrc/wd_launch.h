@@ -75,7 +75,8 @@ struct Launch {
   int g5in, g5out;
   int mask;             // Mask
   int fin;              // Fin
-  int prefin;           // Fin of the previous launch's partials, run by block 0 of each slot before its own work
+  int prefin;           // Fin of the previous launch's partials, run before this launch's own work: by block 0
+                        // of each slot in a stencil; by every block (FIN_CG only) in the CG vector update
   int swz;              // 1: XCD-aware block order
   int total_blocks;
   double coef;          // epilogue coefficient when no RhsState is attached
