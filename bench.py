@@ -13,7 +13,7 @@ bytes / measured launch time vs 8 TB/s), time-to-solution, the same solve
 with FP32 and FP16 inner iterations (FP64 reliable updates), and the CPU
 oracle timed on a bounded sample.
 
-Other workloads: --workload cfg1|cfg3|cfg4|cfg5 (see the design doc for each).
+Other workloads: --workload cfg1|cfg3|cfg4|cfg5|stencil|pion.
 """
 
 import argparse
@@ -511,6 +511,54 @@ def bench_cfg4(args):
                         "mixed_kappa_36rhs": stress, "stencil_12rhs": roof})
 
 
+def bench_pion(args):
+    """16^3x32 (the cfg2 field), kappa 0.1365: the 12 point-source propagators by
+    the even-odd D x = b solve and the zero-momentum pion correlator."""
+    import numpy as np
+    import torch
+    from paper_2409_03030_amd import wdirac as W
+    L, width, kappa, U, _ = make_workload("cfg2")
+    half = L[0] * L[1] * L[2] * L[3] // 2
+    Ud = torch.from_numpy(U).cuda()
+    lat = W.Lattice(L, BC)
+    for prec in ("f64", "f32", "f16"):
+        lat.set_gauge(Ud, prec, 12)
+        for nrhs in (1, 4):
+            lat.autotune(prec, nrhs)
+    res = {}
+    for inner in ("f32", "f16", "f64"):
+        p = W.default_params(inner=inner, delta=1e-2 if inner != "f64" else 0.0)
+        for _ in range(max(1, args.warmup)):
+            S, st = lat.propagator(kappa, params=p)
+            lat.pion_correlator(S)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            S, st = lat.propagator(kappa, params=p)
+            torch.cuda.synchronize()
+        tprop = (time.perf_counter() - t0) / args.steps
+        t0 = time.perf_counter()
+        n_c = 20
+        for _ in range(n_c):
+            C = lat.pion_correlator(S)
+        tcorr = (time.perf_counter() - t0) / n_c
+        res[inner] = {"propagators_ms": tprop * 1e3, "correlator_ms": tcorr * 1e3,
+                      "time_to_correlator_ms": (tprop + tcorr) * 1e3,
+                      "iters": [s["iters"] for s in st], "all_converged": all(s["status"] == 0 for s in st),
+                      "dw_gflops": sum(dw_flops(s, half) for s in st) / tprop / 1e9,
+                      "correlator": [float(v) for v in C]}
+        log(f"pion, {inner} inner: 12 propagators {tprop * 1e3:.1f} ms, correlator {tcorr * 1e3:.2f} ms, "
+            f"iters {min(res[inner]['iters'])}..{max(res[inner]['iters'])}")
+    best = min(res, key=lambda k: res[k]["time_to_correlator_ms"])
+    C = np.array(res[best]["correlator"])
+    meff = [float(np.log(C[t] / C[t + 1])) for t in range(len(C) // 2)]
+    return _common_out(args, res[best]["dw_gflops"], "GFLOP/s", res[best]["time_to_correlator_ms"], best,
+                       {"workload": "16^3x32, U=exp(0.3iH), kappa=0.1365: 12 point-source propagators by the "
+                                    "even-odd D x = b solve (one batched solve), then the zero-momentum pion "
+                                    "correlator", "lattice": list(L), "nrhs": 12, "best_inner": best},
+                       {"by_inner": res, "effective_mass_log_ratio": meff})
+
+
 def bench_cfg5(args):
     """Served stream: Poisson arrivals at 50/s over four lattice sizes, continuous batching."""
     import threading
@@ -667,7 +715,7 @@ def main():
         bench_default(args)
         return
     fn = {"cfg1": bench_cfg1, "cfg3": bench_cfg3, "cfg4": bench_cfg4, "cfg5": bench_cfg5,
-          "stencil": bench_stencil}.get(args.workload)
+          "stencil": bench_stencil, "pion": bench_pion}.get(args.workload)
     if fn is None:
         raise SystemExit(f"unknown workload {args.workload}")
     print(json.dumps(fn(args)), flush=True)

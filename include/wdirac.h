@@ -172,6 +172,45 @@ wd_status wd_solve_DdagD(wd_lattice lat, void* x, const void* b, int32_t nrhs, c
                          const wd_solve_params* params, void* ws, size_t ws_bytes,
                          wd_solve_stats* stats, void* stream);
 
+/* ---- solving D x = b, propagators and the pion correlator -------------- */
+
+/* Workspace bytes for wd_solve_D with these parameters and nrhs fields. */
+size_t wd_solve_D_workspace_bytes(wd_lattice lat, const wd_solve_params* params, int32_t nrhs);
+
+/* Solve D x = b (dagger = 0) or D^dag x = b (dagger = 1) for nrhs full-lattice
+ * fields; the paper's solve_DinvX!(y, D, x) and solve_DinvX!(y, D', x)
+ * (App. C, "Definition of Dirac operators").  kappa[r] (host) is the hopping
+ * parameter of rhs r.  x and b are device fields in the boundary layout with
+ * every site used (both parities, whatever params->precond says).
+ *   WD_EO  : Schur complement.  b'_e = b_e + kappa H_eo b_o; CG on
+ *            D_hat^dag D_hat x_e = D_hat^dag b'_e; x_o = b_o + kappa H_oe x_e.
+ *   WD_FULL: CG on the normal equations D^dag D x = D^dag b.
+ * The adjoint system is solved as D (g5 x) = g5 b.  The pre- and post-steps
+ * run in FP64 with the FP64 gauge store; the CG is wd_solve_DdagD's (mixed
+ * precision and reliable updates per params).  stats (host, nrhs entries)
+ * describe that CG: its residual is the one of the normal equations, to
+ * params->tol.  Blocks the host.  Errors as wd_solve_DdagD; x is written only
+ * when the CG ran (WD_OK, WD_ENOTCONVERGED, WD_ENONFINITE). */
+wd_status wd_solve_D(wd_lattice lat, void* x, const void* b, int32_t nrhs, const double* kappa,
+                     int32_t dagger, const wd_solve_params* params, void* ws, size_t ws_bytes,
+                     wd_solve_stats* stats, void* stream);
+
+/* Workspace bytes for wd_pion_correlator on this lattice. */
+size_t wd_pion_workspace_bytes(wd_lattice lat);
+
+/* Zero-momentum pion correlator of Wilson quarks (the paper's momentum-
+ * projected Wilson pion correlator, Sec. 2 and App. D):
+ *   corr[t] = sum over the spatial sites of time slice (t0 + t) mod Lt, over the
+ *             nsrc propagator columns and over spin and colour, of |S|^2,
+ * for t = 0 .. Lt-1.  S (device, boundary layout, nsrc fields back to back)
+ * holds the solutions of D S_k = point source k, usually the 12 spin-colour
+ * sources at a site of time slice t0; by gamma5-hermiticity the pion
+ * contraction tr[g5 S g5 g5 S^dag g5] is this sum of squared moduli.  FP64
+ * sums in a fixed order (deterministic).  corr is a host array of Lt doubles.
+ * Blocks the host. */
+wd_status wd_pion_correlator(wd_lattice lat, double* corr, const void* S, int32_t nsrc, int32_t t0,
+                             void* ws, size_t ws_bytes, void* stream);
+
 /* ---- batched solve over several lattices in one launch sequence ------- */
 
 typedef struct {

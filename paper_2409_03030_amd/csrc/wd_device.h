@@ -127,7 +127,11 @@ template <> struct SpinorFmt<F16> {
     float m = 0.f;
 #pragma unroll
     for (int k = 0; k < 12; ++k) m = fmaxf(m, fmaxf(fabsf(s.c[k].re), fabsf(s.c[k].im)));
-    float inv = m > 0.f ? 1.0f / m : 0.f;
+    // A site whose largest component is below the smallest normal float is
+    // stored as zero: 1/m would overflow to infinity and poison the site
+    // (such sites appear at the edge of a point source's support).
+    if (m < 1.17549435e-38f) m = 0.f;
+    const float inv = m > 0.f ? 1.0f / m : 0.f;
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
       h8 d;

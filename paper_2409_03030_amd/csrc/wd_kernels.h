@@ -30,4 +30,14 @@ hipError_t launch_spinor_import(const void* src, void* dst, size_t pstride, cons
 hipError_t launch_spinor_export(const void* src, size_t pstride, void* dst, const Geom& g, int nrhs,
                                 int parities, int prec, hipStream_t stream);
 
+// v <- g5 v on `parities` FP64 parity blocks (pstride bytes apart) of ne
+// elements each.
+hipError_t launch_gamma5_f64(void* v, size_t pstride, size_t ne, int parities, hipStream_t stream);
+
+// Pion correlator of nsrc propagator columns S (complex128 boundary layout):
+// block partials (Lt * pion_shares(Lt) doubles) then corr[Lt] (device).
+int pion_shares(int Lt);
+hipError_t launch_pion(const void* S, const Geom& g, int nsrc, int t0, double* partial, double* corr,
+                       hipStream_t stream);
+
 }  // namespace wd

@@ -100,6 +100,11 @@ _SIGS = [
     ("wd_solve_params_default", None, [C.POINTER(SolveParams)]),
     ("wd_solve_DdagD", C.c_int32, [_P, _P, _P, C.c_int32, C.POINTER(C.c_double), C.POINTER(SolveParams), _P,
                                    C.c_size_t, C.POINTER(SolveStats), _P]),
+    ("wd_solve_D_workspace_bytes", C.c_size_t, [_P, C.POINTER(SolveParams), C.c_int32]),
+    ("wd_solve_D", C.c_int32, [_P, _P, _P, C.c_int32, C.POINTER(C.c_double), C.c_int32, C.POINTER(SolveParams), _P,
+                               C.c_size_t, C.POINTER(SolveStats), _P]),
+    ("wd_pion_workspace_bytes", C.c_size_t, [_P]),
+    ("wd_pion_correlator", C.c_int32, [_P, C.POINTER(C.c_double), _P, C.c_int32, C.c_int32, _P, C.c_size_t, _P]),
     ("wd_batch_workspace_bytes", C.c_size_t, [C.c_int32, C.POINTER(SolveRequest), C.POINTER(SolveParams)]),
     ("wd_solve_batch", C.c_int32, [C.c_int32, C.POINTER(SolveRequest), C.POINTER(SolveParams), _P, C.c_size_t,
                                    C.POINTER(SolveStats), _P]),
@@ -289,6 +294,53 @@ class Lattice:
         if check and st not in (WD_OK,):
             _check(st, "wd_solve_DdagD")
         return x, [s.as_dict() for s in stats]
+
+    def solve_D(self, b, kappa, params=None, dagger=False, out=None, stream=None, check=True):
+        """x with D x = b (or D^dag x = b); every site of b and x is used.
+        Returns (x, [stats dict per rhs]) with the stats of the normal-equation CG."""
+        torch = _torch()
+        params = params or default_params()
+        nrhs = None if b.dim() == 6 else b.shape[0]
+        _check_field(b, self._field_shape(nrhs), "b")
+        n = 1 if nrhs is None else nrhs
+        kap = [float(kappa)] * n if not hasattr(kappa, "__len__") else [float(k) for k in kappa]
+        if len(kap) != n:
+            raise ValueError("need one kappa per rhs")
+        x = torch.empty_like(b) if out is None else out
+        nb = int(lib().wd_solve_D_workspace_bytes(self.handle, C.byref(params), n))
+        ws = self._workspace(nb, b.device, ("solve_D", params.inner, params.precond, n))
+        stats = (SolveStats * n)()
+        ka = (C.c_double * n)(*kap)
+        st = lib().wd_solve_D(self.handle, _ptr(x), _ptr(b), n, ka, int(bool(dagger)), C.byref(params), _ptr(ws),
+                              ws.numel(), stats, _stream(stream))
+        if check and st not in (WD_OK,):
+            _check(st, "wd_solve_D")
+        return x, [s.as_dict() for s in stats]
+
+    def propagator(self, kappa, params=None, origin=(0, 0, 0, 0), stream=None, device="cuda"):
+        """The 12 point-source solutions S[3*alpha + a] of D S = delta_{x,origin} e_alpha e_a."""
+        torch = _torch()
+        src = torch.zeros((12,) + self._field_shape(None), dtype=torch.complex128, device=device)
+        x, y, z, t = origin
+        for alpha in range(4):
+            for a in range(3):
+                src[3 * alpha + a, t, z, y, x, alpha, a] = 1.0
+        return self.solve_D(src, kappa, params=params, stream=stream)
+
+    def pion_correlator(self, S, t0=0, stream=None):
+        """C(t) = sum over the spatial sites of slice (t0 + t) mod Lt, the columns of S,
+        spin and colour of |S|^2, for t = 0 .. Lt-1 (numpy array)."""
+        import numpy as np
+        if S.dim() != 7 or tuple(S.shape[1:]) != self._field_shape(None):
+            raise ValueError(f"S must be [nsrc, {self._field_shape(None)}]")
+        _check_field(S, tuple(S.shape), "S")
+        nb = int(lib().wd_pion_workspace_bytes(self.handle))
+        ws = self._workspace(nb, S.device, ("pion",))
+        Lt = self.L[3]
+        out = (C.c_double * Lt)()
+        _check(lib().wd_pion_correlator(self.handle, out, _ptr(S), int(S.shape[0]), int(t0), _ptr(ws), ws.numel(),
+                                        _stream(stream)), "wd_pion_correlator")
+        return np.array(out[:], dtype=np.float64)
 
     def time_hop(self, prec="f64", nrhs=1, n=50, mode=0, stream=None):
         """Mean duration (ms) of n back-to-back stencil launches; mode 0 plain,

@@ -64,6 +64,34 @@ def test_lattice_argument_checks():
     assert lib.wd_lattice_destroy(h) == W.WD_OK
 
 
+def test_solve_D_and_pion_argument_checks():
+    lib = W.lib()
+    h = C.c_void_p()
+    assert lib.wd_lattice_create(C.byref(h), (C.c_int32 * 4)(4, 4, 4, 8), (C.c_int32 * 4)(1, 1, 1, -1)) == W.WD_OK
+    dummy = C.c_void_p(256)
+    p = W.default_params()
+    stats = (W.SolveStats * 1)()
+    k = (C.c_double * 1)(0.1)
+    assert lib.wd_solve_D(h, None, dummy, 1, k, 0, C.byref(p), dummy, 1 << 30, stats, None) == W.WD_EINVAL
+    assert lib.wd_solve_D(h, dummy, dummy, 1, k, 2, C.byref(p), dummy, 1 << 30, stats, None) == W.WD_EINVAL
+    assert lib.wd_solve_D(h, dummy, dummy, 0, k, 0, C.byref(p), dummy, 1 << 30, stats, None) == W.WD_EINVAL
+    assert lib.wd_solve_D(h, dummy, dummy, 1, k, 0, C.byref(p), dummy, 1 << 30, stats, None) == W.WD_ENOGAUGE
+    n1 = lib.wd_solve_D_workspace_bytes(h, C.byref(p), 1)
+    n4 = lib.wd_solve_D_workspace_bytes(h, C.byref(p), 4)
+    # the D^dag D solve's workspace plus the boundary-layout source and FP64 fields
+    assert n1 > lib.wd_solver_workspace_bytes(h, C.byref(p), 1) + 4 * 4 * 4 * 8 * 12 * 16
+    assert n4 > 3 * n1
+    corr = (C.c_double * 8)()
+    nw = lib.wd_pion_workspace_bytes(h)
+    assert nw >= 8 * 8
+    assert lib.wd_pion_correlator(h, corr, dummy, 12, 8, dummy, nw, None) == W.WD_EINVAL   # t0 = Lt
+    assert lib.wd_pion_correlator(h, corr, dummy, 12, -1, dummy, nw, None) == W.WD_EINVAL
+    assert lib.wd_pion_correlator(h, corr, dummy, 0, 0, dummy, nw, None) == W.WD_EINVAL
+    assert lib.wd_pion_correlator(h, corr, dummy, 12, 0, dummy, nw - 1, None) == W.WD_EBUFSIZE
+    assert lib.wd_pion_correlator(h, None, dummy, 12, 0, dummy, nw, None) == W.WD_EINVAL
+    assert lib.wd_lattice_destroy(h) == W.WD_OK
+
+
 def test_default_params():
     p = W.default_params()
     assert p.tol == 1e-10 and p.inner == W.F64 and p.precond == W.EO and p.use_graph == 1
