@@ -13,7 +13,7 @@ bytes / measured launch time vs 8 TB/s), time-to-solution, the same solve
 with FP32 and FP16 inner iterations (FP64 reliable updates), and the CPU
 oracle timed on a bounded sample.
 
-Other workloads: --workload cfg1|cfg3|cfg4|cfg5|stencil|pion.
+Other workloads: --workload cfg1|cfg3|cfg4|cfg5|stencil|pion|force.
 """
 
 import argparse
@@ -559,6 +559,55 @@ def bench_pion(args):
                        {"by_inner": res, "effective_mass_log_ratio": meff})
 
 
+def bench_force(args):
+    """16^3x32 (the cfg2 field), kappa 0.1365: pseudofermion heatbath eta = D^dag xi,
+    then the action and the force U dS_f/dU (two D x = b solves and the force kernel)."""
+    import numpy as np
+    import torch
+    import qcdgen
+    from paper_2409_03030_amd import wdirac as W
+    L, width, kappa, U, _ = make_workload("cfg2")
+    half = L[0] * L[1] * L[2] * L[3] // 2
+    Ud = torch.from_numpy(U).cuda()
+    lat = W.Lattice(L, BC)
+    for prec in ("f64", "f32", "f16"):
+        lat.set_gauge(Ud, prec, 12)
+        lat.autotune(prec, 1)
+    xi = torch.from_numpy(qcdgen.gaussian_spinor(L, qcdgen.rng(qcdgen.CONFIG_SEED_BASE + 5))).cuda()
+    eta = lat.pseudofermion(xi, kappa)
+    xx = float(torch.vdot(xi.flatten(), xi.flatten()).real)
+    res = {}
+    for inner in ("f32", "f16", "f64"):
+        p = W.default_params(inner=inner, delta=1e-2 if inner != "f64" else 0.0)
+        for _ in range(max(1, args.warmup)):
+            lat.fermion_force(eta, kappa, params=p)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            F, S, st = lat.fermion_force(eta, kappa, params=p)
+        torch.cuda.synchronize()
+        tf = (time.perf_counter() - t0) / args.steps
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            _, Sa, _ = lat.fermion_force(eta, kappa, params=p, force=False)
+        torch.cuda.synchronize()
+        ta = (time.perf_counter() - t0) / args.steps
+        res[inner] = {"force_and_action_ms": tf * 1e3, "action_only_ms": ta * 1e3,
+                      "iters": [st[0]["iters"], st[1]["iters"]],
+                      "action_rel_to_xi2": S / xx - 1.0,
+                      "dw_gflops": (dw_flops(st[0], half) + dw_flops(st[1], half)) / tf / 1e9,
+                      "force_norm": float(torch.linalg.vector_norm(F).item())}
+        log(f"force, {inner} inner: {tf * 1e3:.1f} ms (action alone {ta * 1e3:.1f} ms), "
+            f"S/xi^2 - 1 = {S / xx - 1.0:.2e}, iters {st[0]['iters']}+{st[1]['iters']}")
+    best = min(res, key=lambda k: res[k]["force_and_action_ms"])
+    return _common_out(args, res[best]["dw_gflops"], "GFLOP/s", res[best]["force_and_action_ms"], best,
+                       {"workload": "16^3x32, U=exp(0.3iH), kappa=0.1365: pseudofermion action "
+                                    "eta^dag (D^dag D)^-1 eta and force U dS/dU for eta = D^dag xi "
+                                    "(two even-odd D x = b solves and the force kernel)",
+                        "lattice": list(L), "best_inner": best},
+                       {"by_inner": res})
+
+
 def bench_cfg5(args):
     """Served stream: Poisson arrivals at 50/s over four lattice sizes, continuous batching."""
     import threading
@@ -715,7 +764,7 @@ def main():
         bench_default(args)
         return
     fn = {"cfg1": bench_cfg1, "cfg3": bench_cfg3, "cfg4": bench_cfg4, "cfg5": bench_cfg5,
-          "stencil": bench_stencil, "pion": bench_pion}.get(args.workload)
+          "stencil": bench_stencil, "pion": bench_pion, "force": bench_force}.get(args.workload)
     if fn is None:
         raise SystemExit(f"unknown workload {args.workload}")
     print(json.dumps(fn(args)), flush=True)

@@ -211,6 +211,40 @@ size_t wd_pion_workspace_bytes(wd_lattice lat);
 wd_status wd_pion_correlator(wd_lattice lat, double* corr, const void* S, int32_t nsrc, int32_t t0,
                              void* ws, size_t ws_bytes, void* stream);
 
+/* ---- pseudofermion action and force (molecular dynamics) -------------- */
+
+/* eta = D^dag xi: the pseudofermion heatbath (the paper's
+ * sample_pseudofermions! from a Gaussian xi, App. C, "Hybrid Monte Carlo"),
+ * after which S_f(eta) = xi^dag xi.  One field, FP64, full lattice; needs
+ * wd_apply_workspace_bytes(lat, WD_F64, 1).  Asynchronous. */
+wd_status wd_pseudofermion_heatbath(wd_lattice lat, void* eta, const void* xi, double kappa,
+                                    void* ws, size_t ws_bytes, void* stream);
+
+/* Workspace bytes for wd_fermion_force with these parameters. */
+size_t wd_fermion_force_workspace_bytes(wd_lattice lat, const wd_solve_params* params);
+
+/* The pseudofermion action S_f = eta^dag (D^dag D)^{-1} eta and its
+ * derivative "U dS_f/dU" (the paper's evaluate_FermiAction and calc_UdSfdU,
+ * App. C, "Definition of fermion actions").  Solves D^dag Y = eta and D X = Y
+ * with wd_solve_D (params; stats[0], stats[1] describe the two solves), then
+ *   *action  = ||Y||^2                                         (host; may be NULL)
+ *   F_mu(x)  = 2 kappa s_mu(x) U_mu(x) [ M + N^dag ]           (device; may be NULL)
+ *   M = sum_s ((1 - g_mu) X(x+mu))_s Y(x)_s^dag,  N = sum_s ((1 + g_mu) X(x))_s Y(x+mu)_s^dag
+ * (colour outer products summed over spin; s_mu(x) the boundary sign of the
+ * link).  For U_mu(x) -> exp(eps T) U_mu(x), T traceless antihermitian,
+ * dS_f/deps = Re tr[T F_mu(x)].  eta: one complex128 field, boundary layout;
+ * F: complex128 [mu][t][z][y][x][3][3].  When only the action is requested the
+ * second solve is skipped.  Blocks the host; errors as wd_solve_D. */
+wd_status wd_fermion_force(wd_lattice lat, void* F, double* action, const void* eta, double kappa,
+                           const wd_solve_params* params, void* ws, size_t ws_bytes,
+                           wd_solve_stats* stats, void* stream);
+
+/* p_mu(x) += factor * TA(F_mu(x)) with TA(M) = (M - M^dag)/2 - tr(M - M^dag)/6:
+ * the momentum update of the paper's P_update_fermion
+ * (Traceless_antihermitian_add!, factor = -eps * dtau).  p and F are device
+ * complex128 [mu][t][z][y][x][3][3]; p may not overlap F.  Asynchronous. */
+wd_status wd_ta_add(wd_lattice lat, void* p, double factor, const void* F, void* stream);
+
 /* ---- batched solve over several lattices in one launch sequence ------- */
 
 typedef struct {

@@ -8,4 +8,4 @@ from .wilson import *  # noqa: F401,F403
 from .wilson import GAMMA, GAMMA5, ONE4  # noqa: F401
 from .propagator import point_propagator, pion_correlator, residual_D, solve_D  # noqa: F401
 from .force import fermion_action, fermion_force, momentum_update, pseudofermion_heatbath  # noqa: F401
-from .force import traceless_antihermitian  # noqa: F401
+from .force import force_from_solutions, traceless_antihermitian  # noqa: F401

@@ -61,7 +61,12 @@ def fermion_force(U, eta, kappa, bc, tol: float = 1e-12):
     Returns (F, S_f, CG info)."""
     X, info = cg(lambda v: apply_DdagD(U, v, kappa, bc), eta, tol=tol)
     Y = apply_D(U, X, kappa, bc)
-    L = lattice_extents(eta.shape)
+    return force_from_solutions(U, X, Y, kappa, bc), float(vdot(eta, X).real), info
+
+
+def force_from_solutions(U, X, Y, kappa, bc):
+    """The force formula above for given X and Y = D X."""
+    L = lattice_extents(X.shape)
     F = np.empty_like(U)
     for mu in range(4):
         Xf = shift_forward(X, mu)
@@ -72,8 +77,7 @@ def fermion_force(U, eta, kappa, bc, tol: float = 1e-12):
         N = np.einsum("...sb,...sa->...ba", PpX, np.conj(Yf))
         sgn = eta_forward(L, bc, mu)[..., None, None]
         F[mu] = 2.0 * kappa * sgn * (U[mu] @ (M + np.conj(np.swapaxes(N, -1, -2))))
-    S = float(vdot(eta, X).real)
-    return F, S, info
+    return F
 
 
 def traceless_antihermitian(M):

@@ -1,5 +1,6 @@
-// Solving D x = b and D^dag x = b on top of the D^dag D solver, and the
-// pion contraction of point-source propagators (C ABI).
+// Solving D x = b and D^dag x = b on top of the D^dag D solver, the pion
+// contraction of point-source propagators, and the pseudofermion action,
+// force and momentum update (C ABI).
 //
 // Even-odd (Schur complement; D = [[1, -k H_eo], [-k H_oe, 1]] in the
 // (even, odd) blocks):
@@ -74,6 +75,37 @@ wd_status hop64(wd_lattice_s* lat, int nrhs, int mode, int parity, const void* i
   finish_launch(L);
   WD_HIP(launch_hop(L, F64, recon, mode, s));
   return WD_OK;
+}
+
+struct FLayout {
+  size_t yb, xb;   // complex128 boundary fields Y = D^-dag eta, X = D^-1 Y
+  size_t xi, yi;   // the same in the FP64 internal layout (two parity blocks each)
+  size_t pion;     // time-slice sums of |Y|^2 for the action
+  size_t solve;    // workspace of one wd_solve_D
+  size_t total;
+  size_t vb;
+};
+
+FLayout f_layout(wd_lattice_s* lat, const wd_solve_params& p) {
+  FLayout l;
+  const size_t n = (size_t)lat->g.n;
+  l.vb = vec_bytes(F64, n, 1);
+  const size_t field = align_up(2 * n * 12 * 16);
+  size_t o = 0;
+  l.yb = o;
+  o += field;
+  l.xb = o;
+  o += field;
+  l.xi = o;
+  o += 2 * l.vb;
+  l.yi = o;
+  o += 2 * l.vb;
+  l.pion = o;
+  o += align_up(wd_pion_workspace_bytes(lat));
+  l.solve = o;
+  o += wd_solve_D_workspace_bytes(lat, &p, 1);
+  l.total = o;
+  return l;
 }
 
 }  // namespace
@@ -185,6 +217,65 @@ wd_status wd_solve_D(wd_lattice lat, void* x, const void* b, int32_t nrhs, const
   }
   if (cg != WD_OK) set_error("%s", msg.c_str());
   return cg;
+}
+
+size_t wd_fermion_force_workspace_bytes(wd_lattice lat, const wd_solve_params* params) {
+  if (!lat || !params) return 0;
+  return f_layout(lat, *params).total;
+}
+
+wd_status wd_pseudofermion_heatbath(wd_lattice lat, void* eta, const void* xi, double kappa, void* ws,
+                                    size_t ws_bytes, void* stream) {
+  return wd_apply_D(lat, eta, xi, 1, kappa, 1, WD_FULL, WD_F64, ws, ws_bytes, stream);
+}
+
+wd_status wd_fermion_force(wd_lattice lat, void* F, double* action, const void* eta, double kappa,
+                           const wd_solve_params* params, void* ws, size_t ws_bytes, wd_solve_stats* stats,
+                           void* stream) {
+  if (!lat || !eta || !params || !ws || !stats) return fail(WD_EINVAL, "null argument");
+  if (!F && !action) return fail(WD_EINVAL, "neither the force nor the action requested");
+  if (!std::isfinite(kappa)) return fail(WD_EINVAL, "kappa not finite");
+  wd_status s = check_params(*params);
+  if (s != WD_OK) return s;
+  if (!lat->store[F64].ptr) return fail(WD_ENOGAUGE, "the FP64 gauge store is needed");
+  const FLayout l = f_layout(lat, *params);
+  if (ws_bytes < l.total) return fail(WD_EBUFSIZE, "workspace holds %zu bytes, %zu needed", ws_bytes, l.total);
+  memset(stats, 0, 2 * sizeof(wd_solve_stats));
+  hipStream_t st = (hipStream_t)stream;
+  char* w = (char*)ws;
+  void* Yb = w + l.yb;
+  void* Xb = w + l.xb;
+  const Geom& g = lat->g;
+  // Y = D^-dag eta: the action is ||Y||^2 = eta^dag (D^dag D)^{-1} eta
+  s = wd_solve_D(lat, Yb, eta, 1, &kappa, 1, params, w + l.solve, l.total - l.solve, &stats[0], stream);
+  if (s != WD_OK) return s;
+  if (action) {
+    const int Lt = lat->L[3];
+    std::vector<double> slices((size_t)Lt);
+    if ((s = wd_pion_correlator(lat, slices.data(), Yb, 1, 0, w + l.pion, l.solve - l.pion, stream)) != WD_OK)
+      return s;
+    double a = 0.0;
+    for (int t = 0; t < Lt; ++t) a += slices[(size_t)t];
+    *action = a;
+  }
+  if (!F) return WD_OK;
+  // X = D^-1 Y = (D^dag D)^{-1} eta
+  s = wd_solve_D(lat, Xb, Yb, 1, &kappa, 0, params, w + l.solve, l.total - l.solve, &stats[1], stream);
+  if (s != WD_OK) return s;
+  WD_HIP(launch_spinor_import(Xb, w + l.xi, l.vb, g, 1, 2, F64, st));
+  WD_HIP(launch_spinor_import(Yb, w + l.yi, l.vb, g, 1, 2, F64, st));
+  float bc[4];
+  for (int mu = 0; mu < 4; ++mu) bc[mu] = (float)lat->bc[mu];
+  WD_HIP(launch_force(w + l.xi, w + l.yi, l.vb, lat->store[F64].ptr, lat->store[F64].recon, g, bc, kappa, F, st));
+  WD_HIP(hipStreamSynchronize(st));
+  return WD_OK;
+}
+
+wd_status wd_ta_add(wd_lattice lat, void* p, double factor, const void* F, void* stream) {
+  if (!lat || !p || !F) return fail(WD_EINVAL, "null argument");
+  if (!std::isfinite(factor)) return fail(WD_EINVAL, "factor not finite");
+  WD_HIP(launch_ta_add(p, F, factor, 8LL * lat->g.n, (hipStream_t)stream));
+  return WD_OK;
 }
 
 size_t wd_pion_workspace_bytes(wd_lattice lat) {

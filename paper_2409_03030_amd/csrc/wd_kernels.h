@@ -40,4 +40,13 @@ int pion_shares(int Lt);
 hipError_t launch_pion(const void* S, const Geom& g, int nsrc, int t0, double* partial, double* corr,
                        hipStream_t stream);
 
+// Pseudofermion force F_mu(x) = U dS_f/dU from X = (D^dag D)^{-1} eta and
+// Y = D X (FP64 internal fields, one rhs, parity blocks pstride bytes apart)
+// and the FP64 link store; F complex128 [mu][t][z][y][x][3][3].
+hipError_t launch_force(const void* X, const void* Y, size_t pstride, const void* gauge, int recon, const Geom& g,
+                        const float bc[4], double kappa, void* F, hipStream_t stream);
+
+// p += factor * TA(F) over nmat 3x3 complex128 matrices.
+hipError_t launch_ta_add(void* p, const void* F, double factor, long long nmat, hipStream_t stream);
+
 }  // namespace wd

@@ -105,6 +105,11 @@ _SIGS = [
                                C.c_size_t, C.POINTER(SolveStats), _P]),
     ("wd_pion_workspace_bytes", C.c_size_t, [_P]),
     ("wd_pion_correlator", C.c_int32, [_P, C.POINTER(C.c_double), _P, C.c_int32, C.c_int32, _P, C.c_size_t, _P]),
+    ("wd_pseudofermion_heatbath", C.c_int32, [_P, _P, _P, C.c_double, _P, C.c_size_t, _P]),
+    ("wd_fermion_force_workspace_bytes", C.c_size_t, [_P, C.POINTER(SolveParams)]),
+    ("wd_fermion_force", C.c_int32, [_P, _P, C.POINTER(C.c_double), _P, C.c_double, C.POINTER(SolveParams), _P,
+                                     C.c_size_t, C.POINTER(SolveStats), _P]),
+    ("wd_ta_add", C.c_int32, [_P, _P, C.c_double, _P, _P]),
     ("wd_batch_workspace_bytes", C.c_size_t, [C.c_int32, C.POINTER(SolveRequest), C.POINTER(SolveParams)]),
     ("wd_solve_batch", C.c_int32, [C.c_int32, C.POINTER(SolveRequest), C.POINTER(SolveParams), _P, C.c_size_t,
                                    C.POINTER(SolveStats), _P]),
@@ -341,6 +346,45 @@ class Lattice:
         _check(lib().wd_pion_correlator(self.handle, out, _ptr(S), int(S.shape[0]), int(t0), _ptr(ws), ws.numel(),
                                         _stream(stream)), "wd_pion_correlator")
         return np.array(out[:], dtype=np.float64)
+
+    def pseudofermion(self, xi, kappa, out=None, stream=None):
+        """eta = D^dag xi (pseudofermion heatbath from a Gaussian xi)."""
+        torch = _torch()
+        _check_field(xi, self._field_shape(None), "xi")
+        eta = torch.empty_like(xi) if out is None else out
+        nb = int(lib().wd_apply_workspace_bytes(self.handle, PREC["f64"], 1))
+        ws = self._workspace(nb, xi.device, ("apply", PREC["f64"], 1))
+        _check(lib().wd_pseudofermion_heatbath(self.handle, _ptr(eta), _ptr(xi), float(kappa), _ptr(ws), ws.numel(),
+                                               _stream(stream)), "wd_pseudofermion_heatbath")
+        return eta
+
+    def fermion_force(self, eta, kappa, params=None, force=True, stream=None, check=True):
+        """(F, S_f, [stats of the two solves]): F_mu(x) = U dS_f/dU as a
+        [4, Lt, Lz, Ly, Lx, 3, 3] complex128 tensor (None when force=False) and
+        S_f = eta^dag (D^dag D)^{-1} eta."""
+        torch = _torch()
+        params = params or default_params()
+        _check_field(eta, self._field_shape(None), "eta")
+        F = torch.empty((4,) + self.site_shape + (3, 3), dtype=torch.complex128, device=eta.device) if force else None
+        nb = int(lib().wd_fermion_force_workspace_bytes(self.handle, C.byref(params)))
+        ws = self._workspace(nb, eta.device, ("force", params.inner, params.precond))
+        stats = (SolveStats * 2)()
+        act = C.c_double()
+        st = lib().wd_fermion_force(self.handle, _ptr(F) if force else None, C.byref(act), _ptr(eta), float(kappa),
+                                    C.byref(params), _ptr(ws), ws.numel(), stats, _stream(stream))
+        if check and st != WD_OK:
+            _check(st, "wd_fermion_force")
+        return F, act.value, [s.as_dict() for s in stats]
+
+    def ta_add(self, p, factor, F, stream=None):
+        """p += factor * TA(F) in place (momentum update); returns p."""
+        shape = (4,) + self.site_shape + (3, 3)
+        for t, name in ((p, "p"), (F, "F")):
+            torch = _torch()
+            if t.dtype != torch.complex128 or not t.is_cuda or not t.is_contiguous() or tuple(t.shape) != shape:
+                raise ValueError(f"{name} must be a contiguous complex128 CUDA tensor of shape {shape}")
+        _check(lib().wd_ta_add(self.handle, _ptr(p), float(factor), _ptr(F), _stream(stream)), "wd_ta_add")
+        return p
 
     def time_hop(self, prec="f64", nrhs=1, n=50, mode=0, stream=None):
         """Mean duration (ms) of n back-to-back stencil launches; mode 0 plain,

@@ -92,6 +92,27 @@ def test_solve_D_and_pion_argument_checks():
     assert lib.wd_lattice_destroy(h) == W.WD_OK
 
 
+def test_force_argument_checks():
+    lib = W.lib()
+    h = C.c_void_p()
+    assert lib.wd_lattice_create(C.byref(h), (C.c_int32 * 4)(4, 4, 4, 4), (C.c_int32 * 4)(1, 1, 1, -1)) == W.WD_OK
+    dummy = C.c_void_p(256)
+    p = W.default_params()
+    stats = (W.SolveStats * 2)()
+    act = C.c_double()
+    big = 1 << 30
+    assert lib.wd_fermion_force(h, None, None, dummy, 0.1, C.byref(p), dummy, big, stats, None) == W.WD_EINVAL
+    assert lib.wd_fermion_force(h, dummy, C.byref(act), None, 0.1, C.byref(p), dummy, big, stats, None) == W.WD_EINVAL
+    assert lib.wd_fermion_force(h, dummy, C.byref(act), dummy, float("nan"), C.byref(p), dummy, big, stats,
+                                None) == W.WD_EINVAL
+    assert lib.wd_fermion_force(h, dummy, C.byref(act), dummy, 0.1, C.byref(p), dummy, big, stats, None) == W.WD_ENOGAUGE
+    n = lib.wd_fermion_force_workspace_bytes(h, C.byref(p))
+    assert n > lib.wd_solve_D_workspace_bytes(h, C.byref(p), 1) + 2 * 4 ** 4 * 192
+    assert lib.wd_ta_add(h, None, 0.1, dummy, None) == W.WD_EINVAL
+    assert lib.wd_ta_add(h, dummy, float("inf"), dummy, None) == W.WD_EINVAL
+    assert lib.wd_lattice_destroy(h) == W.WD_OK
+
+
 def test_default_params():
     p = W.default_params()
     assert p.tol == 1e-10 and p.inner == W.F64 and p.precond == W.EO and p.use_graph == 1
