@@ -121,6 +121,23 @@ def calibration_copy():
     return 2.0 * (1 << 30) / dt / 1e9
 
 
+def read_bandwidth():
+    """A 1 GiB streaming read (torch's sum over 2^28 floats): a reference for
+    what a plain read-only kernel reaches on the same box."""
+    import torch
+    a = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+    a.sum()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(5):
+        a.sum()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / 5
+    del a
+    torch.cuda.empty_cache()
+    return float(1 << 30) / dt / 1e9
+
+
 def dw_flops(stats, half_sites, eo=True):
     """Useful D_W flops of a solve: 1320 per stencil output site."""
     hops_per_iter = 4 if eo else 4  # EO: 4 half-lattice hops; FULL: 2 full-lattice = 4 half
@@ -287,6 +304,7 @@ def bench_default(args):
     cgr_ms = lat.time_hop("f64", 1, n=200, mode=2)
     cgr_bytes = half * (8 * (16 * (9 if recon64 == 18 else 6)) + 4 * 192)
     copy_gbs = calibration_copy()
+    read_gbs = read_bandwidth()
     cpu = None
     if not args.no_cpu_baseline:
         log(f"timing the CPU oracle for ~{args.cpu_seconds:.0f} s ...")
@@ -338,6 +356,7 @@ def bench_default(args):
                                      "launches": roof["hop_launches"], "gflops": roof["gflops"]},
         },
         "copy_1GiB_gbs": copy_gbs,
+        "read_1GiB_gbs": read_gbs,
         "mixed_precision": mixed,
         "cpu_baseline": cpu,
     }
@@ -731,6 +750,9 @@ def bench_stencil(args):
     torch.cuda.synchronize()
     cp = (time.perf_counter() - t0) / 5
     res["copy_1GiB"] = {"ms": cp * 1e3, "gbs_read_plus_write": 2 * (1 << 30) / cp / 1e9}
+    del a, b
+    torch.cuda.empty_cache()
+    res["read_1GiB_gbs"] = read_bandwidth()
     best = res["f64-18"]
     return _common_out(args, best["gbs"], "GB/s", best["ms"], "f64",
                        {"workload": f"stencil only: one even-odd hop (V/2 output sites) on {'x'.join(map(str, L))}"},

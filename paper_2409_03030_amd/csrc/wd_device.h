@@ -9,6 +9,8 @@
 #include <hip/hip_fp16.h>
 #include <stdint.h>
 
+#include <utility>
+
 #define WD_HD __host__ __device__ __forceinline__
 
 // Native vector type for non-temporal loads (the builtin takes clang vectors).
@@ -441,6 +443,17 @@ template <typename TO, typename TI> WD_HD void spinor_convert(spinor<TO>& o, con
 // The hopping term at one output site: acc = H in (optionally gamma5 on in).
 // gauge points at the start of the store; in points at the input parity
 // block.  ne = n * nrhs is the chunk stride of the spinor block.
+//
+// Hop h (0..7) is direction mu = h / 2, forward for even h and backward for
+// odd h.  FP64 and FP32 run each hop in turn (hop_dir: spinor load,
+// projection, link load, product), relying on the waves in flight to hide
+// the latency.  FP16, whose stencil is bound by instruction issue rather than
+// memory, fetches the spinors and links of 4 hops first (all their loads in
+// flight together, no branch between them) and then computes them.  Measured
+// on one box with the same launch shapes: the grouped form was 2-4 % faster
+// for FP16 (24^3x48, 32^3x64), but 4 % slower for the FP64 CG-residual
+// stencil (19.8 against 19.0 us at 16^3x32) and 1 % slower for FP32; at
+// FP64 a group of 2 hops took the 2-way split to one wave per SIMD.
 // ---------------------------------------------------------------------------
 template <int P, int R, int MU, int DIR>
 WD_HD void hop_dir(const Geom& g, const Coord& k, int parity, int s, int rhs, int nrhs,
@@ -472,52 +485,110 @@ WD_HD void hop_dir(const Geom& g, const Coord& k, int parity, int s, int rhs, in
   accumulate<MU, DIR>(acc, gh);
 }
 
-// Both hops along direction MU (forward then backward).
-template <int P, int R, int MU>
-WD_HD void hop_mu(const Geom& g, const Coord& k, int parity, int s, int rhs, int nrhs, const char* gauge,
-                  const void* in, const float bc[4], bool g5in, spinor<typename RealOf<P>::T>& acc) {
-  hop_dir<P, R, MU, +1>(g, k, parity, s, rhs, nrhs, gauge, in, bc[MU], g5in, acc);
-  hop_dir<P, R, MU, -1>(g, k, parity, s, rhs, nrhs, gauge, in, bc[MU], g5in, acc);
+template <int P> struct HopBuf {
+  spinor<typename RealOf<P>::T> p;  // neighbour spinor
+  su3<typename RealOf<P>::T> u;     // U_mu(x) (forward) or U_mu(x - mu) (backward)
+  bool flip;                        // the hop crosses a boundary with sign -1
+};
+
+
+template <int P, int R, int H>
+WD_HD void hop_fetch(const Geom& g, const Coord& k, int parity, int s, int rhs, int nrhs, const char* gauge,
+                     const void* in, const float bc[4], HopBuf<P>& b) {
+  constexpr int MU = H >> 1;
+  constexpr int DIR = (H & 1) ? -1 : 1;
+  const size_t n = (size_t)g.n;
+  const size_t ne = n * (size_t)nrhs;
+  const int nb = neighbour_cb(g, k, MU, DIR);
+  SpinorFmt<P>::load(in, ne, (size_t)nb * nrhs + rhs, b.p);
+  // forward: U_mu(x), rooted at the output site (parity `parity`);
+  // backward: U_mu(x - mu), rooted at the neighbour (other parity).
+  const int lp = DIR > 0 ? parity : 1 - parity;
+  const size_t ls = DIR > 0 ? (size_t)s : (size_t)nb;
+  const char* lbase = gauge + (size_t)(lp * 4 + MU) * link_dir_bytes<P, R>(n);
+  LinkFmt<P, R>::load(lbase, n, ls, b.u);
+  const bool crosses = DIR > 0 ? (k.c[MU] == g.L[MU] - 1) : (k.c[MU] == 0);
+  b.flip = crosses && bc[MU] < 0.f;
+}
+
+template <int P, int H>
+WD_HD void hop_finish(HopBuf<P>& b, bool g5in, spinor<typename RealOf<P>::T>& acc) {
+  using T = typename RealOf<P>::T;
+  constexpr int MU = H >> 1;
+  constexpr int DIR = (H & 1) ? -1 : 1;
+  if (g5in) gamma5_inplace(b.p);
+  half_spinor<T> h, gh;
+  project<MU, DIR>(b.p, h);
+  if (b.flip) {
+#pragma unroll
+    for (int j = 0; j < 6; ++j) h.c[j] = cneg(h.c[j]);
+  }
+  if (DIR > 0) mul_link(b.u, h, gh);
+  else mul_link_dag(b.u, h, gh);
+  accumulate<MU, DIR>(acc, gh);
+}
+
+template <int P, int R, int H0, int... J>
+WD_HD void hop_fetch_group(std::integer_sequence<int, J...>, const Geom& g, const Coord& k, int parity, int s,
+                           int rhs, int nrhs, const char* gauge, const void* in, const float bc[4], HopBuf<P>* b) {
+  (hop_fetch<P, R, H0 + J>(g, k, parity, s, rhs, nrhs, gauge, in, bc, b[J]), ...);
+}
+
+template <int P, int H0, int... J>
+WD_HD void hop_finish_group(std::integer_sequence<int, J...>, HopBuf<P>* b, bool g5in,
+                            spinor<typename RealOf<P>::T>& acc) {
+  (hop_finish<P, H0 + J>(b[J], g5in, acc), ...);
+}
+
+// Hops H0 .. H0 + NH - 1, accumulated in hop order (FP16 in groups of 4).
+template <int P, int R, int H0, int NH>
+WD_HD void hop_range(const Geom& g, const Coord& k, int parity, int s, int rhs, int nrhs, const char* gauge,
+                     const void* in, const float bc[4], bool g5in, spinor<typename RealOf<P>::T>& acc) {
+  if constexpr (NH > 0 && P != F16) {
+    constexpr int MU = H0 >> 1;
+    constexpr int DIR = (H0 & 1) ? -1 : 1;
+    hop_dir<P, R, MU, DIR>(g, k, parity, s, rhs, nrhs, gauge, in, bc[MU], g5in, acc);
+    hop_range<P, R, H0 + 1, NH - 1>(g, k, parity, s, rhs, nrhs, gauge, in, bc, g5in, acc);
+  } else if constexpr (NH > 0) {
+    constexpr int M = NH < 4 ? NH : 4;
+    HopBuf<P> b[M];
+    hop_fetch_group<P, R, H0>(std::make_integer_sequence<int, M>{}, g, k, parity, s, rhs, nrhs, gauge, in, bc, b);
+    hop_finish_group<P, H0>(std::make_integer_sequence<int, M>{}, b, g5in, acc);
+    hop_range<P, R, H0 + M, NH - M>(g, k, parity, s, rhs, nrhs, gauge, in, bc, g5in, acc);
+  }
 }
 
 // The share `part` of the 8 hops when they are split over D threads:
 // D = 1 all directions, D = 2 (x,y) / (z,t), D = 4 one direction each,
-// D = 8 one hop each.
+// D = 8 one hop each.  Parts are whole waves, so the branch on `part` is
+// uniform.
 template <int P, int R, int D>
 WD_HD void hop_part(const Geom& g, int parity, int s, int rhs, int nrhs, const char* gauge, const void* in,
                     const float bc[4], bool g5in, int part, spinor<typename RealOf<P>::T>& acc) {
   Coord k = site_coord(g, parity, s);
   spinor_zero(acc);
-  if (D == 1) {
-    hop_mu<P, R, 0>(g, k, parity, s, rhs, nrhs, gauge, in, bc, g5in, acc);
-    hop_mu<P, R, 1>(g, k, parity, s, rhs, nrhs, gauge, in, bc, g5in, acc);
-    hop_mu<P, R, 2>(g, k, parity, s, rhs, nrhs, gauge, in, bc, g5in, acc);
-    hop_mu<P, R, 3>(g, k, parity, s, rhs, nrhs, gauge, in, bc, g5in, acc);
-  } else if (D == 2) {
-    if (part == 0) {
-      hop_mu<P, R, 0>(g, k, parity, s, rhs, nrhs, gauge, in, bc, g5in, acc);
-      hop_mu<P, R, 1>(g, k, parity, s, rhs, nrhs, gauge, in, bc, g5in, acc);
-    } else {
-      hop_mu<P, R, 2>(g, k, parity, s, rhs, nrhs, gauge, in, bc, g5in, acc);
-      hop_mu<P, R, 3>(g, k, parity, s, rhs, nrhs, gauge, in, bc, g5in, acc);
-    }
-  } else if (D == 4) {
+  if constexpr (D == 1) {
+    hop_range<P, R, 0, 8>(g, k, parity, s, rhs, nrhs, gauge, in, bc, g5in, acc);
+  } else if constexpr (D == 2) {
+    if (part == 0) hop_range<P, R, 0, 4>(g, k, parity, s, rhs, nrhs, gauge, in, bc, g5in, acc);
+    else hop_range<P, R, 4, 4>(g, k, parity, s, rhs, nrhs, gauge, in, bc, g5in, acc);
+  } else if constexpr (D == 4) {
     switch (part) {
-      case 0: hop_mu<P, R, 0>(g, k, parity, s, rhs, nrhs, gauge, in, bc, g5in, acc); break;
-      case 1: hop_mu<P, R, 1>(g, k, parity, s, rhs, nrhs, gauge, in, bc, g5in, acc); break;
-      case 2: hop_mu<P, R, 2>(g, k, parity, s, rhs, nrhs, gauge, in, bc, g5in, acc); break;
-      default: hop_mu<P, R, 3>(g, k, parity, s, rhs, nrhs, gauge, in, bc, g5in, acc); break;
+      case 0: hop_range<P, R, 0, 2>(g, k, parity, s, rhs, nrhs, gauge, in, bc, g5in, acc); break;
+      case 1: hop_range<P, R, 2, 2>(g, k, parity, s, rhs, nrhs, gauge, in, bc, g5in, acc); break;
+      case 2: hop_range<P, R, 4, 2>(g, k, parity, s, rhs, nrhs, gauge, in, bc, g5in, acc); break;
+      default: hop_range<P, R, 6, 2>(g, k, parity, s, rhs, nrhs, gauge, in, bc, g5in, acc); break;
     }
   } else {
     switch (part) {
-      case 0: hop_dir<P, R, 0, +1>(g, k, parity, s, rhs, nrhs, gauge, in, bc[0], g5in, acc); break;
-      case 1: hop_dir<P, R, 0, -1>(g, k, parity, s, rhs, nrhs, gauge, in, bc[0], g5in, acc); break;
-      case 2: hop_dir<P, R, 1, +1>(g, k, parity, s, rhs, nrhs, gauge, in, bc[1], g5in, acc); break;
-      case 3: hop_dir<P, R, 1, -1>(g, k, parity, s, rhs, nrhs, gauge, in, bc[1], g5in, acc); break;
-      case 4: hop_dir<P, R, 2, +1>(g, k, parity, s, rhs, nrhs, gauge, in, bc[2], g5in, acc); break;
-      case 5: hop_dir<P, R, 2, -1>(g, k, parity, s, rhs, nrhs, gauge, in, bc[2], g5in, acc); break;
-      case 6: hop_dir<P, R, 3, +1>(g, k, parity, s, rhs, nrhs, gauge, in, bc[3], g5in, acc); break;
-      default: hop_dir<P, R, 3, -1>(g, k, parity, s, rhs, nrhs, gauge, in, bc[3], g5in, acc); break;
+      case 0: hop_range<P, R, 0, 1>(g, k, parity, s, rhs, nrhs, gauge, in, bc, g5in, acc); break;
+      case 1: hop_range<P, R, 1, 1>(g, k, parity, s, rhs, nrhs, gauge, in, bc, g5in, acc); break;
+      case 2: hop_range<P, R, 2, 1>(g, k, parity, s, rhs, nrhs, gauge, in, bc, g5in, acc); break;
+      case 3: hop_range<P, R, 3, 1>(g, k, parity, s, rhs, nrhs, gauge, in, bc, g5in, acc); break;
+      case 4: hop_range<P, R, 4, 1>(g, k, parity, s, rhs, nrhs, gauge, in, bc, g5in, acc); break;
+      case 5: hop_range<P, R, 5, 1>(g, k, parity, s, rhs, nrhs, gauge, in, bc, g5in, acc); break;
+      case 6: hop_range<P, R, 6, 1>(g, k, parity, s, rhs, nrhs, gauge, in, bc, g5in, acc); break;
+      default: hop_range<P, R, 7, 1>(g, k, parity, s, rhs, nrhs, gauge, in, bc, g5in, acc); break;
     }
   }
 }
