@@ -13,7 +13,7 @@ bytes / measured launch time vs 8 TB/s), time-to-solution, the same solve
 with FP32 and FP16 inner iterations (FP64 reliable updates), and the CPU
 oracle timed on a bounded sample.
 
-Other workloads: --workload cfg1|cfg3|cfg4|cfg5|stencil|pion|force.
+Other workloads: --workload cfg1|cfg3|cfg4|cfg5|stencil|pion|force|staggered.
 """
 
 import argparse
@@ -627,6 +627,54 @@ def bench_force(args):
                        {"by_inner": res})
 
 
+def bench_staggered(args):
+    """16^3x32 (the cfg2 field), staggered operator with mass 0.1: D x = b by the
+    even-odd CG on M_e = m^2 - H_eo H_oe, plain FP64 and FP32 inner iterations."""
+    import numpy as np
+    import torch
+    import qcdgen
+    from paper_2409_03030_amd import wdirac as W
+    L, width, _, U, _ = make_workload("cfg2")
+    mass = 0.1
+    half = L[0] * L[1] * L[2] * L[3] // 2
+    Ud = torch.from_numpy(U).cuda()
+    lat = W.Lattice(L, BC)
+    for prec in ("f64", "f32"):
+        lat.set_gauge(Ud, prec, 12)
+    g = qcdgen.rng(qcdgen.CONFIG_SEED_BASE + 6)
+    shape = qcdgen.site_shape(L) + (3,)
+    b = torch.from_numpy(g.standard_normal(shape) + 1j * g.standard_normal(shape)).cuda()
+    res = {}
+    for inner in ("f64", "f32"):
+        p = W.default_params(inner=inner, delta=1e-2 if inner != "f64" else 0.0)
+        for _ in range(max(1, args.warmup)):
+            lat.stag_solve(b, mass, params=p)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            x, st = lat.stag_solve(b, mass, params=p)
+        torch.cuda.synchronize()
+        tt = (time.perf_counter() - t0) / args.steps
+        pt = W.SolveParams.from_buffer_copy(p)
+        pt.timing = 1
+        _, sti = lat.stag_solve(b, mass, params=pt)
+        s0 = sti[0]
+        n = st[0]["iters"] + st[0]["reliable_updates"]
+        res[inner] = {"time_to_solution_ms": tt * 1e3, "iters": st[0]["iters"],
+                      "reliable_updates": st[0]["reliable_updates"], "true_resid": st[0]["true_resid"],
+                      "dw_gflops": 570.0 * half * 2 * n / tt / 1e9,
+                      "stencil_gbs": s0["hop_bytes"] / (s0["hop_ms"] * 1e-3) / 1e9,
+                      "stencil_ms_avg": s0["hop_ms"] / max(1, s0["hop_launches"])}
+        log(f"staggered, {inner} inner: {st[0]['iters']} iters, {tt * 1e3:.2f} ms, "
+            f"stencil {res[inner]['stencil_gbs']:.0f} GB/s")
+    best = min(res, key=lambda k: res[k]["time_to_solution_ms"])
+    return _common_out(args, res[best]["dw_gflops"], "GFLOP/s", res[best]["time_to_solution_ms"], best,
+                       {"workload": "16^3x32, U=exp(0.3iH), staggered mass 0.1, even-odd CG on m^2 - H_eo H_oe "
+                                    "to true residual 1e-10, then x_o", "lattice": list(L), "mass": mass,
+                        "best_inner": best},
+                       {"by_inner": res, "flop_per_site": 570})
+
+
 def bench_cfg5(args):
     """Served stream: Poisson arrivals at 50/s over four lattice sizes, continuous batching."""
     import threading
@@ -786,7 +834,8 @@ def main():
         bench_default(args)
         return
     fn = {"cfg1": bench_cfg1, "cfg3": bench_cfg3, "cfg4": bench_cfg4, "cfg5": bench_cfg5,
-          "stencil": bench_stencil, "pion": bench_pion, "force": bench_force}.get(args.workload)
+          "stencil": bench_stencil, "pion": bench_pion, "force": bench_force,
+          "staggered": bench_staggered}.get(args.workload)
     if fn is None:
         raise SystemExit(f"unknown workload {args.workload}")
     print(json.dumps(fn(args)), flush=True)

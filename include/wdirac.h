@@ -245,6 +245,41 @@ wd_status wd_fermion_force(wd_lattice lat, void* F, double* action, const void* 
  * complex128 [mu][t][z][y][x][3][3]; p may not overlap F.  Asynchronous. */
 wd_status wd_ta_add(wd_lattice lat, void* p, double factor, const void* F, void* stream);
 
+/* ---- staggered fermions ------------------------------------------------- */
+
+/* The paper's second Dirac operator (App. C, "Definition of Dirac operators":
+ * the staggered operator with a mass, applied with mul! and inverted with
+ * solve_DinvX!), in the textbook Kogut-Susskind form on one colour vector per
+ * site:
+ *   (D chi)(x) = m chi(x) + 1/2 sum_mu eta_mu(x) [ s+ U_mu(x) chi(x+mu) - s- U_mu(x-mu)^dag chi(x-mu) ]
+ * with eta_1 = 1, eta_2 = (-1)^x, eta_3 = (-1)^(x+y), eta_4 = (-1)^(x+y+z) and the
+ * lattice's boundary signs s+/s-.  The hopping part is anti-Hermitian, so
+ * D^dag = m - (hopping part).  Fields: complex128 [rhs][t][z][y][x][colour 3].
+ * The gauge stores registered with wd_set_gauge serve both operators. */
+
+/* Workspace bytes for wd_stag_apply. */
+size_t wd_stag_apply_workspace_bytes(wd_lattice lat, int32_t prec, int32_t nrhs);
+
+/* y = D x (dagger = 0) or D^dag x (dagger = 1) on the full lattice, at FP64 or
+ * FP32 with that precision's gauge store.  Asynchronous. */
+wd_status wd_stag_apply(wd_lattice lat, void* y, const void* x, int32_t nrhs, double mass, int32_t dagger,
+                        int32_t prec, void* ws, size_t ws_bytes, void* stream);
+
+/* Workspace bytes for wd_stag_solve with these parameters and nrhs fields. */
+size_t wd_stag_solve_workspace_bytes(wd_lattice lat, const wd_solve_params* params, int32_t nrhs);
+
+/* Solve D x = b (dagger = 0) or D^dag x = b (dagger = 1) for nrhs fields with
+ * per-rhs masses (host, finite and nonzero).  Even-odd: b'_e = m b_e - s H_eo b_o,
+ * CG on the Hermitian positive definite even block M_e = m^2 - H_eo H_oe, then
+ * x_o = (b_o - s H_oe x_e) / m (s = +1 for D, -1 for D^dag).  The CG is the
+ * engine of wd_solve_DdagD: FP64 or FP32 inner iterations (params->inner) with
+ * FP64 reliable updates, stopping on the true FP64 residual of M_e x_e = b'_e
+ * at params->tol; params->precond must be WD_EO.  stats (host, nrhs entries)
+ * describe that CG.  Blocks the host; errors as wd_solve_DdagD. */
+wd_status wd_stag_solve(wd_lattice lat, void* x, const void* b, int32_t nrhs, const double* mass, int32_t dagger,
+                        const wd_solve_params* params, void* ws, size_t ws_bytes, wd_solve_stats* stats,
+                        void* stream);
+
 /* ---- batched solve over several lattices in one launch sequence ------- */
 
 typedef struct {

@@ -19,7 +19,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libwdirac.so")
 
-SOURCES = ["hop.hip", "blas.hip", "measure.hip", "force.hip", "host.cpp", "engine.cpp", "server.cpp", "dsolve.cpp"]
+SOURCES = ["hop.hip", "blas.hip", "measure.hip", "force.hip", "stag.hip", "host.cpp", "engine.cpp", "server.cpp", "dsolve.cpp", "stag_api.cpp"]
 
 ARCH = os.environ.get("WD_OFFLOAD_ARCH", "gfx950")
 

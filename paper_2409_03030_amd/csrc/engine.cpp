@@ -31,12 +31,17 @@ int min_sblk(int nrhs) {
 
 size_t states_bytes(size_t nstates) { return align_up(nstates * sizeof(RhsState)); }
 
-ItemLayout item_layout(const wd_lattice_s* lat, const wd_solve_params& p, int nrhs) {
+size_t field_bytes(int op, int prec, size_t n, int nrhs) {
+  if (op == OP_WILSON) return vec_bytes(prec, n, nrhs);
+  return align_up(n * (size_t)nrhs * 3 * (prec == F64 ? 16 : 8));  // colour vectors, FP64 or FP32
+}
+
+ItemLayout item_layout(const wd_lattice_s* lat, const wd_solve_params& p, int nrhs, int op) {
   ItemLayout l;
   const size_t n = (size_t)lat->g.n;
   const int np = p.precond == WD_EO ? 1 : 2;
-  const int P = p.inner, A = acc_prec(P);
-  const size_t vh = vec_bytes(F64, n, nrhs), va = vec_bytes(A, n, nrhs), vp = vec_bytes(P, n, nrhs);
+  const int P = p.inner, A = op == OP_WILSON ? acc_prec(P) : P;
+  const size_t vh = field_bytes(op, F64, n, nrhs), va = field_bytes(op, A, n, nrhs), vp = field_bytes(op, P, n, nrhs);
   size_t o = 0;
   l.off_partial = o;
   o += align_up((size_t)np * ((n + min_sblk(nrhs) - 1) / min_sblk(nrhs)) * nrhs * sizeof(double));
@@ -153,7 +158,7 @@ wd_status Engine::run_phase(const std::vector<EItem*>& list, const Phase& ph0) {
     if (ph.fold_small && ph.prefin != FIN_NONE && !folded) L.prefin = FIN_NONE;
     if (hash_) {
       // key of a captured block: every launch's kernel choice and arguments
-      const int id[4] = {ph.hop ? 1 : 0, ph.prec, recon, ph.mode};
+      const int id[5] = {ph.hop ? 1 : 0, ph.prec, recon, ph.mode, op_};
       *hash_ = fnv1a(*hash_, id, sizeof id);
       *hash_ = fnv1a(*hash_, &L, sizeof L);
       i = j;
@@ -162,13 +167,16 @@ wd_status Engine::run_phase(const std::vector<EItem*>& list, const Phase& ph0) {
     if (ph.hop) {
       hipError_t e = timer_ ? timer_->begin(stream_) : hipSuccess;
       if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
-      e = launch_hop(L, ph.prec, recon, ph.mode, stream_);
+      e = op_ == OP_STAG ? launch_stag(L, ph.prec, recon, ph.mode, stream_)
+                         : launch_hop(L, ph.prec, recon, ph.mode, stream_);
       if (e != hipSuccess) return hip_fail(e, "stencil launch");
-      e = timer_ ? timer_->end(stream_, sites, hop_launch_bytes(ph.prec, recon, ph.mode, sites, nrhs), ph.mode)
-                 : hipSuccess;
+      const double bytes = op_ == OP_STAG ? stag_launch_bytes(ph.prec, recon, ph.mode, sites, nrhs)
+                                          : hop_launch_bytes(ph.prec, recon, ph.mode, sites, nrhs);
+      e = timer_ ? timer_->end(stream_, sites, bytes, op_ == OP_STAG ? 0 : ph.mode) : hipSuccess;
       if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
     } else {
-      hipError_t e = launch_blas(L, ph.prec, ph.mode, stream_);
+      hipError_t e = op_ == OP_STAG ? launch_sblas(L, ph.prec, ph.mode, stream_)
+                                    : launch_blas(L, ph.prec, ph.mode, stream_);
       if (e != hipSuccess) return hip_fail(e, "vector kernel launch");
     }
     if (ph.fin != FIN_NONE && !ph.fin_folded && !folded) {
@@ -196,8 +204,16 @@ wd_status Engine::run_iteration() {
       {true, -1, HOP_CGR, 2, 1, 1, MASK_ACTIVE, FIN_CG, R_T2, R_NONE, R_T2, FIN_NONE, false, true},
       {false, -1, BLAS_CGUPD, 2, 0, 0, MASK_ACTIVE, FIN_NONE, R_NONE, R_P, R_NONE, FIN_CG, false, true},
   };
-  const Phase* k = eo_ ? eo : full;
-  const int nk = eo_ ? 5 : 3;
+  // Staggered (even block M_e = m^2 - H_eo H_oe, c = m^2): alpha needs the
+  // whole <p, M_e p> before the residual update, so its reduction is finished
+  // by its own small kernel.
+  static const Phase st[3] = {
+      {true, -1, S_NORM, 1, 0, 0, MASK_RUN, FIN_ALPHA, R_P, R_T1, R_P, FIN_NONE, false},
+      {true, -1, S_CGR, 0, 0, 0, MASK_ACTIVE, FIN_CG, R_T1, R_NONE, R_P, FIN_NONE, false, true},
+      {false, -1, BLAS_CGUPD, 0, 0, 0, MASK_ACTIVE, FIN_NONE, R_NONE, R_P, R_NONE, FIN_CG, false, true},
+  };
+  const Phase* k = op_ == OP_STAG ? st : eo_ ? eo : full;
+  const int nk = op_ == OP_STAG ? 3 : eo_ ? 5 : 3;
   for (int q = 0; q < nk; ++q) {
     wd_status s = run_phase(items, k[q]);
     if (s != WD_OK) return s;
@@ -220,8 +236,14 @@ wd_status Engine::run_reliable() {
       {true, F64, HOP_RESID, 2, 1, 1, MASK_HOLD, FIN_RESID, R_H2, R_NONE, R_H2, FIN_NONE, false},
       {false, -1, BLAS_RU_FIN, 2, 0, 0, MASK_RU, FIN_NONE, R_NONE, R_P, R_NONE, FIN_NONE, false},
   };
-  const Phase* k = eo_ ? eo : full;
-  const int nk = eo_ ? 6 : 4;
+  static const Phase st[4] = {
+      {false, -1, BLAS_RU_ACC, 0, 0, 0, MASK_HOLD, FIN_NONE, R_NONE, R_P, R_NONE, FIN_NONE, false},
+      {true, F64, S_PLAIN, 1, 0, 0, MASK_HOLD, FIN_NONE, R_XH, R_H1, R_NONE, FIN_NONE, false},
+      {true, F64, S_RESID, 0, 0, 0, MASK_HOLD, FIN_RESID, R_H1, R_NONE, R_XH, FIN_NONE, false},
+      {false, -1, BLAS_RU_FIN, 0, 0, 0, MASK_RU, FIN_NONE, R_NONE, R_P, R_NONE, FIN_NONE, false},
+  };
+  const Phase* k = op_ == OP_STAG ? st : eo_ ? eo : full;
+  const int nk = op_ == OP_STAG ? 4 : eo_ ? 6 : 4;
   for (int q = 0; q < nk; ++q) {
     wd_status s = run_phase(items, k[q]);
     if (s != WD_OK) return s;
@@ -237,13 +259,17 @@ wd_status Engine::start_item(EItem* it) {
     const double k = it->kappa[r];
     s.stop2 = p_.tol * p_.tol;
     s.delta2 = p_.delta * p_.delta;
-    s.c = eo_ ? k * k : k;
+    s.c = (eo_ || op_ == OP_STAG) ? k * k : k;  // kappa^2, kappa, or the staggered m^2
     s.maxiter = p_.maxiter;
     s.state = ST_RUN;
   }
   WD_HIP(hipMemcpyAsync(it->st, it->h_init.data(), it->nrhs * sizeof(RhsState), hipMemcpyHostToDevice, stream_));
-  WD_HIP(launch_spinor_import(it->b, it->base + it->lay.off_bh, it->lay.hstride, it->lat->g, it->nrhs, eo_ ? 1 : 2,
+  if (op_ == OP_STAG)
+    WD_HIP(launch_stag_import(it->b, it->base + it->lay.off_bh, it->lay.hstride, it->lat->g, it->nrhs, eo_ ? 1 : 2,
                               F64, stream_));
+  else
+    WD_HIP(launch_spinor_import(it->b, it->base + it->lay.off_bh, it->lay.hstride, it->lat->g, it->nrhs,
+                                eo_ ? 1 : 2, F64, stream_));
   const Phase init = {false, -1, BLAS_INIT, eo_ ? 0 : 2, 0, 0, MASK_NONE, FIN_INIT, R_NONE, R_P, R_NONE, FIN_NONE,
                       false};
   std::vector<EItem*> one{it};
@@ -252,8 +278,12 @@ wd_status Engine::start_item(EItem* it) {
 }
 
 wd_status Engine::export_item(EItem* it) {
-  WD_HIP(launch_spinor_export(it->base + it->lay.off_xh, it->lay.hstride, it->x, it->lat->g, it->nrhs, eo_ ? 1 : 2,
+  if (op_ == OP_STAG)
+    WD_HIP(launch_stag_export(it->base + it->lay.off_xh, it->lay.hstride, it->x, it->lat->g, it->nrhs, eo_ ? 1 : 2,
                               F64, stream_));
+  else
+    WD_HIP(launch_spinor_export(it->base + it->lay.off_xh, it->lay.hstride, it->x, it->lat->g, it->nrhs,
+                                eo_ ? 1 : 2, F64, stream_));
   return WD_OK;
 }
 
@@ -447,14 +477,14 @@ static hipStream_t solve_stream(hipStream_t s, wd_status* st) {
 }
 
 wd_status run_batch(std::vector<EItem>& items, const wd_solve_params& p, RhsState* states, hipStream_t stream_in,
-                    wd_solve_stats* stats) {
+                    wd_solve_stats* stats, int op) {
   auto t0 = std::chrono::steady_clock::now();
   wd_status sst;
   hipStream_t stream = solve_stream(stream_in, &sst);
   if (sst != WD_OK) return sst;
   HopTimer timer;
   timer.on = p.timing != 0;
-  Engine eng(p, stream, states, timer.on ? &timer : nullptr);
+  Engine eng(p, stream, states, timer.on ? &timer : nullptr, op);
   size_t nst = 0;
   for (auto& it : items) nst += (size_t)it.nrhs;
   wd_status result = WD_OK;

@@ -204,6 +204,19 @@ double hop_launch_bytes(int prec, int recon, int mode, long long sites, int nrhs
   return site_sets * 8 * link + (double)sites * vec;
 }
 
+double stag_launch_bytes(int prec, int recon, int mode, long long sites, int nrhs) {
+  const double link = (prec == F64 ? 16.0 : 8.0) * (recon == 12 ? 6 : 9);
+  const double sv = prec == F64 ? 48.0 : 24.0;
+  double vec = 0.0;
+  switch (mode) {
+    case S_PLAIN: vec = 2 * sv; break;               // in, out
+    case S_XPAY: case S_NORM: vec = 3 * sv; break;   // in, aux, out
+    case S_CGR: vec = 4 * sv; break;                 // in, aux, r read + write
+    case S_RESID: vec = 2 * sv + 2 * 48.0; break;    // in, aux, b, r_h
+  }
+  return (double)sites / nrhs * 8 * link + (double)sites * vec;
+}
+
 double HopTimer::total_ms() {
   double t = 0.0;
   for (size_t i = 0; i + 1 < used; i += 2) {

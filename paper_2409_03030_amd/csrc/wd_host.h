@@ -44,6 +44,8 @@ inline int acc_prec(int prec) { return prec == F16 ? F32 : prec; }
 // nrhs fields: 8 links per site (shared by the rhs), the input spinor once,
 // and the epilogue vectors of the mode once each.
 double hop_launch_bytes(int prec, int recon, int mode, long long sites, int nrhs);
+// The same for the staggered stencil (StagMode).
+double stag_launch_bytes(int prec, int recon, int mode, long long sites, int nrhs);
 
 struct Tune {
   int sblk;   // sites per block (power of two; see valid_tune)
@@ -88,7 +90,15 @@ struct ItemLayout {
   size_t hstride, astride, vstride;               // parity strides (FULL mode)
   size_t total;
 };
-ItemLayout item_layout(const wd_lattice_s* lat, const wd_solve_params& p, int nrhs);
+// Operator families the engine runs: the Wilson operator (CG on D^dag D or
+// D_hat^dag D_hat) or the staggered operator (CG on its even block
+// M_e = m^2 - H_eo H_oe; even-odd only, FP64 or FP32 inner).
+enum Op : int { OP_WILSON = 0, OP_STAG = 1 };
+
+// Bytes of one parity block of nrhs fields of the operator's vector type.
+size_t field_bytes(int op, int prec, size_t n, int nrhs);
+
+ItemLayout item_layout(const wd_lattice_s* lat, const wd_solve_params& p, int nrhs, int op = OP_WILSON);
 size_t states_bytes(size_t nstates);
 
 // One solve in an engine.
@@ -116,8 +126,8 @@ struct EItem {
 // item (grouped by nrhs, at most kMaxSlots per launch).
 class Engine {
  public:
-  Engine(const wd_solve_params& p, hipStream_t s, RhsState* states, HopTimer* timer)
-      : p_(p), eo_(p.precond == WD_EO), stream_(s), states_(states), timer_(timer) {}
+  Engine(const wd_solve_params& p, hipStream_t s, RhsState* states, HopTimer* timer, int op = OP_WILSON)
+      : p_(p), eo_(p.precond == WD_EO), op_(op), stream_(s), states_(states), timer_(timer) {}
   std::vector<EItem*> items;
   long long blocks = 0;  // poll blocks enqueued so far
 
@@ -140,6 +150,7 @@ class Engine {
   uint64_t block_key(int K);
   wd_solve_params p_;
   bool eo_;
+  int op_;
   hipStream_t stream_;
   RhsState* states_;
   HopTimer* timer_;
@@ -167,7 +178,7 @@ wd_status stats_from_state(const RhsState& s, double seconds, const HopTimer* t,
 
 // Solve items to completion (no items join later).  Blocks the host.
 wd_status run_batch(std::vector<EItem>& items, const wd_solve_params& p, RhsState* states, hipStream_t stream,
-                    wd_solve_stats* stats);
+                    wd_solve_stats* stats, int op = OP_WILSON);
 
 wd_status check_params(const wd_solve_params& p);
 wd_status check_lattice_for(const wd_lattice_s* lat, int prec, int precond);

@@ -7,6 +7,14 @@
 
 namespace wd {
 
+// Epilogues of the staggered stencil (H = the hopping part, anti-Hermitian):
+//   S_PLAIN: out = H in
+//   S_XPAY : out = c aux + a H in        (c, a) = (st.c, st.alpha) or (coef, coef2)
+//   S_NORM : out = H in; |out|^2 + c |aux|^2 (aux at the output site's index) -> FIN_ALPHA
+//   S_CGR  : r -= alpha (c aux - H in); |r|^2 -> FIN_CG
+//   S_RESID: r_h = b - (c aux - H in); |r_h|^2 -> FIN_RESID (FP64)
+enum StagMode : int { S_PLAIN = 0, S_XPAY = 1, S_NORM = 2, S_CGR = 3, S_RESID = 4 };
+
 // Stencil with epilogue `mode` (HopMode) at precision prec and link recon.
 hipError_t launch_hop(const Launch& L, int prec, int recon, int mode, hipStream_t stream);
 
@@ -48,5 +56,15 @@ hipError_t launch_force(const void* X, const void* Y, size_t pstride, const void
 
 // p += factor * TA(F) over nmat 3x3 complex128 matrices.
 hipError_t launch_ta_add(void* p, const void* F, double factor, long long nmat, hipStream_t stream);
+
+// Staggered stencil (StagMode) and CG vector kernels (BlasMode) at FP64 or
+// FP32; colour-vector layout conversions to and from complex128
+// [rhs][t][z][y][x][3].
+hipError_t launch_stag(const Launch& L, int prec, int recon, int mode, hipStream_t stream);
+hipError_t launch_sblas(const Launch& L, int prec, int mode, hipStream_t stream);
+hipError_t launch_stag_import(const void* src, void* dst, size_t pstride, const Geom& g, int nrhs, int parities,
+                              int prec, hipStream_t stream);
+hipError_t launch_stag_export(const void* src, size_t pstride, void* dst, const Geom& g, int nrhs, int parities,
+                              int prec, hipStream_t stream);
 
 }  // namespace wd

@@ -80,6 +80,7 @@ struct Launch {
   int swz;              // 1: XCD-aware block order
   int total_blocks;
   double coef;          // epilogue coefficient when no RhsState is attached
+  double coef2;         // second coefficient (staggered XPAY) when no RhsState is attached
 };
 
 }  // namespace wd

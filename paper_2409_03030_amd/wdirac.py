@@ -110,6 +110,11 @@ _SIGS = [
     ("wd_fermion_force", C.c_int32, [_P, _P, C.POINTER(C.c_double), _P, C.c_double, C.POINTER(SolveParams), _P,
                                      C.c_size_t, C.POINTER(SolveStats), _P]),
     ("wd_ta_add", C.c_int32, [_P, _P, C.c_double, _P, _P]),
+    ("wd_stag_apply_workspace_bytes", C.c_size_t, [_P, C.c_int32, C.c_int32]),
+    ("wd_stag_apply", C.c_int32, [_P, _P, _P, C.c_int32, C.c_double, C.c_int32, C.c_int32, _P, C.c_size_t, _P]),
+    ("wd_stag_solve_workspace_bytes", C.c_size_t, [_P, C.POINTER(SolveParams), C.c_int32]),
+    ("wd_stag_solve", C.c_int32, [_P, _P, _P, C.c_int32, C.POINTER(C.c_double), C.c_int32, C.POINTER(SolveParams),
+                                  _P, C.c_size_t, C.POINTER(SolveStats), _P]),
     ("wd_batch_workspace_bytes", C.c_size_t, [C.c_int32, C.POINTER(SolveRequest), C.POINTER(SolveParams)]),
     ("wd_solve_batch", C.c_int32, [C.c_int32, C.POINTER(SolveRequest), C.POINTER(SolveParams), _P, C.c_size_t,
                                    C.POINTER(SolveStats), _P]),
@@ -385,6 +390,44 @@ class Lattice:
                 raise ValueError(f"{name} must be a contiguous complex128 CUDA tensor of shape {shape}")
         _check(lib().wd_ta_add(self.handle, _ptr(p), float(factor), _ptr(F), _stream(stream)), "wd_ta_add")
         return p
+
+    def _stag_shape(self, nrhs):
+        base = self.site_shape + (3,)
+        return base if nrhs is None else (nrhs,) + base
+
+    def stag_apply(self, x, mass, dagger=False, prec="f64", out=None, stream=None):
+        """y = D x (or D^dag x) for the staggered operator; x is [(nrhs,) Lt, Lz, Ly, Lx, 3]."""
+        torch = _torch()
+        nrhs = None if x.dim() == 5 else x.shape[0]
+        _check_field(x, self._stag_shape(nrhs), "x")
+        n = 1 if nrhs is None else nrhs
+        y = torch.empty_like(x) if out is None else out
+        nb = int(lib().wd_stag_apply_workspace_bytes(self.handle, PREC[prec], n))
+        ws = self._workspace(nb, x.device, ("stag_apply", PREC[prec], n))
+        _check(lib().wd_stag_apply(self.handle, _ptr(y), _ptr(x), n, float(mass), int(bool(dagger)), PREC[prec],
+                                   _ptr(ws), ws.numel(), _stream(stream)), "wd_stag_apply")
+        return y
+
+    def stag_solve(self, b, mass, params=None, dagger=False, out=None, stream=None, check=True):
+        """x with D x = b (or D^dag x = b) for the staggered operator, even-odd CG.
+        Returns (x, [stats dict per rhs])."""
+        torch = _torch()
+        params = params or default_params()
+        nrhs = None if b.dim() == 5 else b.shape[0]
+        _check_field(b, self._stag_shape(nrhs), "b")
+        n = 1 if nrhs is None else nrhs
+        ms = [float(mass)] * n if not hasattr(mass, "__len__") else [float(m) for m in mass]
+        if len(ms) != n:
+            raise ValueError("need one mass per rhs")
+        x = torch.empty_like(b) if out is None else out
+        nb = int(lib().wd_stag_solve_workspace_bytes(self.handle, C.byref(params), n))
+        ws = self._workspace(nb, b.device, ("stag_solve", params.inner, n))
+        stats = (SolveStats * n)()
+        st = lib().wd_stag_solve(self.handle, _ptr(x), _ptr(b), n, (C.c_double * n)(*ms), int(bool(dagger)),
+                                 C.byref(params), _ptr(ws), ws.numel(), stats, _stream(stream))
+        if check and st != WD_OK:
+            _check(st, "wd_stag_solve")
+        return x, [s.as_dict() for s in stats]
 
     def time_hop(self, prec="f64", nrhs=1, n=50, mode=0, stream=None):
         """Mean duration (ms) of n back-to-back stencil launches; mode 0 plain,

@@ -113,6 +113,33 @@ def test_force_argument_checks():
     assert lib.wd_lattice_destroy(h) == W.WD_OK
 
 
+def test_staggered_argument_checks():
+    lib = W.lib()
+    h = C.c_void_p()
+    assert lib.wd_lattice_create(C.byref(h), (C.c_int32 * 4)(4, 4, 4, 4), (C.c_int32 * 4)(1, 1, 1, -1)) == W.WD_OK
+    dummy = C.c_void_p(256)
+    big = 1 << 30
+    assert lib.wd_stag_apply(h, dummy, dummy, 1, 0.1, 0, W.F16, dummy, big, None) == W.WD_EINVAL
+    assert lib.wd_stag_apply(h, dummy, dummy, 1, 0.1, 2, W.F64, dummy, big, None) == W.WD_EINVAL
+    assert lib.wd_stag_apply(h, dummy, dummy, 1, 0.1, 0, W.F64, dummy, big, None) == W.WD_ENOGAUGE
+    assert lib.wd_stag_apply_workspace_bytes(h, W.F64, 2) == 2 * lib.wd_stag_apply_workspace_bytes(h, W.F64, 1)
+    p = W.default_params()
+    stats = (W.SolveStats * 1)()
+    m = (C.c_double * 1)(0.1)
+    zero = (C.c_double * 1)(0.0)
+    assert lib.wd_stag_solve(h, dummy, dummy, 1, m, 0, C.byref(p), dummy, big, stats, None) == W.WD_ENOGAUGE
+    pf = W.default_params(precond="full")
+    assert lib.wd_stag_solve(h, dummy, dummy, 1, m, 0, C.byref(pf), dummy, big, stats, None) == W.WD_EINVAL
+    p16 = W.default_params(inner="f16")
+    assert lib.wd_stag_solve(h, dummy, dummy, 1, m, 0, C.byref(p16), dummy, big, stats, None) == W.WD_EINVAL
+    assert lib.wd_stag_solve(h, dummy, dummy, 1, zero, 0, C.byref(p), dummy, big, stats, None) in (W.WD_EINVAL,
+                                                                                                  W.WD_ENOGAUGE)
+    n1 = lib.wd_stag_solve_workspace_bytes(h, C.byref(p), 1)
+    # a colour vector is a quarter of a Wilson spinor
+    assert 0 < n1 < lib.wd_solver_workspace_bytes(h, C.byref(p), 1) + 4 ** 4 * 200
+    assert lib.wd_lattice_destroy(h) == W.WD_OK
+
+
 def test_default_params():
     p = W.default_params()
     assert p.tol == 1e-10 and p.inner == W.F64 and p.precond == W.EO and p.use_graph == 1
