@@ -108,8 +108,19 @@ constexpr int kFoldPartials = 1024;
 
 static bool fold_ok(const Launch& L) {
   for (int k = 0; k < L.nslots; ++k)
-    if ((long long)L.s[k].nblk * L.nrhs > kFoldPartials) return false;
+    if ((long long)L.s[k].npart * L.nrhs > kFoldPartials) return false;
   return true;
+}
+
+// Sites per block of the vector kernels: at least 128 threads whatever the
+// stencil's shape, so that a folded stage 2 (every block reading all the
+// stencil's partials) is not repeated by many small blocks.  (Measured at
+// 16^3x32: FP32 stencil blocks of 64 sites made the vector update 4 % of
+// the solve slower; 256-thread blocks were 0.5 % slower than 128 at FP64.)
+static int blas_sblk(int nrhs) {
+  int s = 1;
+  while (2 * s * nrhs <= kBlock / 2) s *= 2;
+  return s;
 }
 
 wd_status Engine::run_phase(const std::vector<EItem*>& list, const Phase& ph0) {
@@ -152,6 +163,18 @@ wd_status Engine::run_phase(const std::vector<EItem*>& list, const Phase& ph0) {
       S.st = it->st;
       S.partial = (double*)(it->base + l.off_partial);
       sites += (long long)it->lat->g.n * (ph.parity == 2 ? 2 : 1) * nrhs;
+    }
+    if (!ph.hop) {
+      // vector kernel: its own block shape; a folded stage 2 still reads the
+      // partials of the stencil launch before it
+      const int sb = std::max(blas_sblk(nrhs), t.sblk);
+      L.sblk = sb;
+      for (size_t k2 = i; k2 < j; ++k2) {
+        Slot& S = L.s[k2 - i];
+        const int npart = S.nblk;
+        fill_slot_geometry(S, list[k2]->lat, sb, ph.parity);
+        if (ph.prefin != FIN_NONE) S.npart = npart;
+      }
     }
     finish_launch(L);
     const bool folded = ph.fold_small && fold_ok(L);

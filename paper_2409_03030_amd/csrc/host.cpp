@@ -123,6 +123,7 @@ void fill_slot_geometry(Slot& S, const wd_lattice_s* lat, int sblk, int parity) 
   for (int mu = 0; mu < 4; ++mu) S.bc[mu] = (float)lat->bc[mu];
   const int nbp = (lat->g.n + sblk - 1) / sblk;
   S.nblk = parity == 2 ? 2 * nbp : nbp;
+  S.npart = S.nblk;
 }
 
 void finish_launch(Launch& L) {

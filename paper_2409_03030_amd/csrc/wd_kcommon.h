@@ -263,7 +263,7 @@ __device__ void reduce_partials(const double* __restrict__ part, int npart, int 
 // the next stencil: sum the partials and run the CG scalar update.
 __device__ void gather_and_finalize(const Launch& L, const Slot& S, int fin) {
   __shared__ double red[kRedSlots];
-  reduce_partials(S.partial, S.nblk, L.nrhs, red);
+  reduce_partials(S.partial, S.npart, L.nrhs, red);
   const int tid = (int)threadIdx.x;
   if (tid < L.nrhs && S.st != nullptr) finalize_rhs(fin, S.st[tid], red[tid]);
   __syncthreads();
@@ -277,7 +277,7 @@ __device__ void gather_and_finalize(const Launch& L, const Slot& S, int fin) {
 // a state after the first block stored it computes the same result.
 __device__ void fold_finalize_cg(const Launch& L, const Slot& S, const Tile& t, double* beta, int* state) {
   __shared__ double red[kRedSlots];
-  reduce_partials(S.partial, S.nblk, L.nrhs, red);
+  reduce_partials(S.partial, S.npart, L.nrhs, red);
   const int tid = (int)threadIdx.x;
   if (tid < L.nrhs) {
     RhsState s = S.st[tid];

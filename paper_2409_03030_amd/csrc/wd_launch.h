@@ -49,6 +49,7 @@ struct Slot {
   float bc[4];
   int blk0;             // first block of the slot in the launch
   int nblk;             // blocks of the slot over all parities of the launch
+  int npart;            // partials finished by this launch (prefin / fold): the producing launch's nblk
   const char* gauge;    // link store of the launch's precision
   const void* in;       // stencil input (P precision), parity block of the input parity
   void* out;            // output (P precision; F64 in HOP_RESID)
