@@ -121,21 +121,15 @@ def calibration_copy():
     return 2.0 * (1 << 30) / dt / 1e9
 
 
-def read_bandwidth():
-    """A 1 GiB streaming read (torch's sum over 2^28 floats): a reference for
-    what a plain read-only kernel reaches on the same box."""
+def read_bandwidth(nbytes=1 << 30):
+    """The library's plain streaming-read kernel over nbytes: the attainable
+    read rate on the same box (1 GiB: from HBM; 128 MiB: partly from the
+    Infinity Cache, like the 16^3x32 working set)."""
     import torch
-    a = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
-    a.sum()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(5):
-        a.sum()
-    torch.cuda.synchronize()
-    dt = (time.perf_counter() - t0) / 5
-    del a
+    from paper_2409_03030_amd import wdirac as W
+    ms = W.time_read(nbytes, n=20 if nbytes <= (256 << 20) else 5)
     torch.cuda.empty_cache()
-    return float(1 << 30) / dt / 1e9
+    return float(nbytes) / (ms * 1e-3) / 1e9
 
 
 def dw_flops(stats, half_sites, eo=True):
@@ -305,6 +299,7 @@ def bench_default(args):
     cgr_bytes = half * (8 * (16 * (9 if recon64 == 18 else 6)) + 4 * 192)
     copy_gbs = calibration_copy()
     read_gbs = read_bandwidth()
+    read128_gbs = read_bandwidth(128 << 20)
     cpu = None
     if not args.no_cpu_baseline:
         log(f"timing the CPU oracle for ~{args.cpu_seconds:.0f} s ...")
@@ -354,9 +349,12 @@ def bench_default(args):
                          "achieved_gbs": roof["cgr_gbs"], "note": "hipEvents around each launch of one solve"},
             "all_stencil_launches": {"achieved_gbs": roof["achieved_gbs"], "avg_launch_ms": roof["hop_ms_avg"],
                                      "launches": roof["hop_launches"], "gflops": roof["gflops"]},
+            "attainable_read_gbs": {"1GiB": read_gbs, "128MiB": read128_gbs,
+                                    "note": "plain streaming-read kernel on the same box"},
         },
         "copy_1GiB_gbs": copy_gbs,
         "read_1GiB_gbs": read_gbs,
+        "read_128MiB_gbs": read128_gbs,
         "mixed_precision": mixed,
         "cpu_baseline": cpu,
     }

@@ -312,6 +312,14 @@ wd_status wd_solve_batch(int32_t nreq, const wd_solve_request* reqs, const wd_so
 wd_status wd_time_hop(wd_lattice lat, int32_t prec, int32_t nrhs, int32_t mode, int32_t n,
                       void* ws, size_t ws_bytes, double* ms_per_launch, void* stream);
 
+/* Time n back-to-back launches of a plain streaming-read kernel over the
+ * device buffer buf (bytes, a positive multiple of 16; 2048 blocks of 256
+ * threads, 16-byte loads with a grid stride): the attainable read rate the
+ * stencils are compared with.  out (device, >= 2048 doubles) receives the
+ * block sums.  *ms_per_read gets the mean duration.  Blocks the host. */
+wd_status wd_time_read(const void* buf, size_t bytes, int32_t n, void* out, size_t out_bytes, double* ms_per_read,
+                       void* stream);
+
 /* Autotune the stencil launch shape (sites per workgroup, XCD-aware block
  * order, number of threads the 8 hops of a site are split over) for this
  * lattice, precision and nrhs by timing every candidate on stream; the choice

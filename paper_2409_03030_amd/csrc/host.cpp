@@ -592,6 +592,32 @@ wd_status wd_time_hop(wd_lattice lat, int32_t prec, int32_t nrhs, int32_t mode, 
   return time_hop_shape(lat, prec, nrhs, mode, n, t, (char*)ws, ms_per_launch, st);
 }
 
+wd_status wd_time_read(const void* buf, size_t bytes, int32_t n, void* out, size_t out_bytes, double* ms_per_read,
+                       void* stream) {
+  if (!buf || !out || !ms_per_read || n < 1) return fail(WD_EINVAL, "bad argument");
+  if (bytes < 16 || bytes % 16) return fail(WD_EINVAL, "bytes must be a positive multiple of 16");
+  const int blocks = 2048;
+  if (out_bytes < blocks * sizeof(double)) return fail(WD_EBUFSIZE, "out holds %zu bytes, %zu needed", out_bytes,
+                                                        blocks * sizeof(double));
+  hipStream_t st = (hipStream_t)stream;
+  hipEvent_t e0, e1;
+  WD_HIP(hipEventCreate(&e0));
+  WD_HIP(hipEventCreate(&e1));
+  hipError_t e = hipSuccess;
+  for (int i = 0; i < 3 && e == hipSuccess; ++i) e = launch_read_probe(buf, bytes, (double*)out, blocks, st);
+  if (e == hipSuccess) e = hipEventRecord(e0, st);
+  for (int i = 0; i < n && e == hipSuccess; ++i) e = launch_read_probe(buf, bytes, (double*)out, blocks, st);
+  if (e == hipSuccess) e = hipEventRecord(e1, st);
+  if (e == hipSuccess) e = hipEventSynchronize(e1);
+  float f = 0.f;
+  if (e == hipSuccess) e = hipEventElapsedTime(&f, e0, e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (e != hipSuccess) return hip_fail(e, "timed reads");
+  *ms_per_read = (double)f / n;
+  return WD_OK;
+}
+
 wd_status wd_autotune(wd_lattice lat, int32_t prec, int32_t nrhs, void* ws, size_t ws_bytes,
                       int32_t* best_sites_per_block, int32_t* best_swizzle, int32_t* best_split, void* stream) {
   wd_status s = check_lattice_for(lat, prec, WD_EO);

@@ -92,4 +92,27 @@ hipError_t launch_pion(const void* S, const Geom& g, int nsrc, int t0, double* p
   return hipGetLastError();
 }
 
+// Streaming-read reference: every thread reads 16-byte chunks of buf with a
+// grid stride and the blocks store their sums (so the loads are not dead).
+__global__ void __launch_bounds__(256) read_probe_kernel(const double2* __restrict__ buf, size_t n,
+                                                         double* __restrict__ out) {
+  __shared__ double w[4];
+  double s = 0.0;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+    const double2 v = buf[i];
+    s += v.x + v.y;
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+  if ((threadIdx.x & 63) == 0) w[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) out[blockIdx.x] = w[0] + w[1] + w[2] + w[3];
+}
+
+hipError_t launch_read_probe(const void* buf, size_t bytes, double* out, int blocks, hipStream_t stream) {
+  hipLaunchKernelGGL(read_probe_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, (const double2*)buf, bytes / 16,
+                     out);
+  return hipGetLastError();
+}
+
 }  // namespace wd

@@ -48,6 +48,10 @@ int pion_shares(int Lt);
 hipError_t launch_pion(const void* S, const Geom& g, int nsrc, int t0, double* partial, double* corr,
                        hipStream_t stream);
 
+// Streaming read of `bytes` (a multiple of 16) by `blocks` blocks of 256
+// threads; one double per block is written to out.
+hipError_t launch_read_probe(const void* buf, size_t bytes, double* out, int blocks, hipStream_t stream);
+
 // Pseudofermion force F_mu(x) = U dS_f/dU from X = (D^dag D)^{-1} eta and
 // Y = D X (FP64 internal fields, one rhs, parity blocks pstride bytes apart)
 // and the FP64 link store; F complex128 [mu][t][z][y][x][3][3].

@@ -120,6 +120,7 @@ _SIGS = [
                                    C.POINTER(SolveStats), _P]),
     ("wd_time_hop", C.c_int32, [_P, C.c_int32, C.c_int32, C.c_int32, C.c_int32, _P, C.c_size_t,
                                 C.POINTER(C.c_double), _P]),
+    ("wd_time_read", C.c_int32, [_P, C.c_size_t, C.c_int32, _P, C.c_size_t, C.POINTER(C.c_double), _P]),
     ("wd_autotune", C.c_int32, [_P, C.c_int32, C.c_int32, _P, C.c_size_t, C.POINTER(C.c_int32),
                                 C.POINTER(C.c_int32), C.POINTER(C.c_int32), _P]),
     ("wd_tune_export", C.c_size_t, [C.c_char_p, C.c_size_t]),
@@ -448,6 +449,17 @@ class Lattice:
         _check(lib().wd_autotune(self.handle, PREC[prec], nrhs, _ptr(ws), ws.numel(), C.byref(sb), C.byref(sw),
                                  C.byref(sp), _stream(stream)), "wd_autotune")
         return sb.value, sw.value, sp.value
+
+
+def time_read(nbytes, n=20, device="cuda", stream=None):
+    """Mean duration (ms) of a plain streaming read of a device buffer of nbytes."""
+    torch = _torch()
+    buf = torch.zeros(nbytes, dtype=torch.uint8, device=device)
+    out = torch.empty(2048, dtype=torch.float64, device=device)
+    ms = C.c_double()
+    _check(lib().wd_time_read(_ptr(buf), nbytes, n, _ptr(out), out.numel() * 8, C.byref(ms), _stream(stream)),
+           "wd_time_read")
+    return ms.value
 
 
 def tune_import(text: str):
