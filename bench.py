@@ -639,6 +639,8 @@ def bench_staggered(args):
     lat = W.Lattice(L, BC)
     for prec in ("f64", "f32"):
         lat.set_gauge(Ud, prec, 12)
+        sb, sw = lat.stag_autotune(prec, 1)
+        log(f"staggered autotune {prec}: sites/block {sb}, xcd swizzle {sw}")
     g = qcdgen.rng(qcdgen.CONFIG_SEED_BASE + 6)
     shape = qcdgen.site_shape(L) + (3,)
     b = torch.from_numpy(g.standard_normal(shape) + 1j * g.standard_normal(shape)).cuda()

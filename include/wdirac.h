@@ -265,6 +265,15 @@ size_t wd_stag_apply_workspace_bytes(wd_lattice lat, int32_t prec, int32_t nrhs)
 wd_status wd_stag_apply(wd_lattice lat, void* y, const void* x, int32_t nrhs, double mass, int32_t dagger,
                         int32_t prec, void* ws, size_t ws_bytes, void* stream);
 
+/* Autotune the staggered stencil's launch shape (sites per workgroup, XCD-
+ * aware block order) for this lattice, precision and nrhs by timing every
+ * candidate on stream (outputs must be bit-identical); the choice is kept in
+ * a process-wide table used by later staggered launches (not part of the
+ * exported text table).  Needs wd_stag_apply_workspace_bytes.  Blocks the
+ * host.  The best_* outputs receive the choice (may be NULL). */
+wd_status wd_stag_autotune(wd_lattice lat, int32_t prec, int32_t nrhs, void* ws, size_t ws_bytes,
+                           int32_t* best_sites_per_block, int32_t* best_swizzle, void* stream);
+
 /* Workspace bytes for wd_stag_solve with these parameters and nrhs fields. */
 size_t wd_stag_solve_workspace_bytes(wd_lattice lat, const wd_solve_params* params, int32_t nrhs);
 

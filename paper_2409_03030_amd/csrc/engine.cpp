@@ -101,14 +101,31 @@ struct Engine::Phase {
   bool fold_small;  // FIN_CG producer / consumer pair: fold when every slot has few partials
 };
 
-// FIN_CG is finished by every block of the following vector kernel when each
-// slot has at most this many block partials (per launch: every block then
-// reads them all, so the fold only pays off while they are few).
+// A reduction is finished by every block of the launch that consumes it
+// (FIN_CG in the vector update, the staggered alpha in its residual update)
+// when each slot has at most kFoldPartials block partials and the consumer's
+// blocks together read at most kFoldReads of them: every block repeats the
+// whole gather, so the fold only pays off while partials and blocks are few.
+// (Measured at 16^3x32: 1024 stencil blocks each gathering 1024 partials
+// cost the staggered FP64 CG about 9 us per iteration, far more than a
+// finalize kernel; 512 vector-update blocks gathering 1024 partials were still
+// 6 us per iteration faster than the finalize kernel in the FP32 Wilson CG.)
 constexpr int kFoldPartials = 1024;
+constexpr long long kFoldReads = 1LL << 19;
 
-static bool fold_ok(const Launch& L) {
-  for (int k = 0; k < L.nslots; ++k)
-    if ((long long)L.s[k].npart * L.nrhs > kFoldPartials) return false;
+// Consumer blocks of a slot: the stencil's own block count, or the vector
+// kernels' (blas_sblk sites per block).
+static int blas_sblk(int nrhs);
+
+static bool fold_ok(const Launch& L, bool consumer_is_blas) {
+  for (int k = 0; k < L.nslots; ++k) {
+    const Slot& S = L.s[k];
+    const long long parts = (long long)S.npart * L.nrhs;
+    if (parts > kFoldPartials) return false;
+    const int sb = consumer_is_blas ? std::max(blas_sblk(L.nrhs), L.sblk) : L.sblk;
+    const long long blocks = ((long long)S.g.n + sb - 1) / sb * (L.parity == 2 ? 2 : 1);
+    if (blocks * parts > kFoldReads) return false;
+  }
   return true;
 }
 
@@ -134,7 +151,7 @@ wd_status Engine::run_phase(const std::vector<EItem*>& list, const Phase& ph0) {
     while (j < list.size() && j - i < (size_t)kMaxSlots && list[j]->nrhs == nrhs) ++j;
     const wd_lattice_s* lat0 = list[i]->lat;
     const int recon = lat0->store[ph.prec].recon;
-    const Tune t = tune_lookup(lat0, ph.prec, recon, nrhs);
+    const Tune t = op_ == OP_STAG ? stag_tune_lookup(lat0, ph.prec, recon, nrhs) : tune_lookup(lat0, ph.prec, recon, nrhs);
     Launch L = base_launch(nrhs, t, ph.parity);
     L.g5in = ph.g5in;
     L.g5out = ph.g5out;
@@ -177,8 +194,11 @@ wd_status Engine::run_phase(const std::vector<EItem*>& list, const Phase& ph0) {
       }
     }
     finish_launch(L);
-    const bool folded = ph.fold_small && fold_ok(L);
-    if (ph.fold_small && ph.prefin != FIN_NONE && !folded) L.prefin = FIN_NONE;
+    // Fold decisions, taken alike by the producing and the consuming launch:
+    // the consumer of a FIN_CG fold is a vector kernel, that of the staggered
+    // alpha fold the residual-update stencil (the producer's geometry).
+    const bool folded = ph.fold_small && ph.fin != FIN_NONE && fold_ok(L, ph.fin == FIN_CG);
+    if (ph.fold_small && ph.prefin != FIN_NONE && !fold_ok(L, !ph.hop)) L.prefin = FIN_NONE;
     if (hash_) {
       // key of a captured block: every launch's kernel choice and arguments
       const int id[5] = {ph.hop ? 1 : 0, ph.prec, recon, ph.mode, op_};
@@ -228,11 +248,12 @@ wd_status Engine::run_iteration() {
       {false, -1, BLAS_CGUPD, 2, 0, 0, MASK_ACTIVE, FIN_NONE, R_NONE, R_P, R_NONE, FIN_CG, false, true},
   };
   // Staggered (even block M_e = m^2 - H_eo H_oe, c = m^2): alpha needs the
-  // whole <p, M_e p> before the residual update, so its reduction is finished
-  // by its own small kernel.
+  // whole <p, M_e p> before the residual update, so every block of that
+  // update finishes the alpha reduction itself when the partials are few (else
+  // a finalize kernel runs between the two stencils).
   static const Phase st[3] = {
-      {true, -1, S_NORM, 1, 0, 0, MASK_RUN, FIN_ALPHA, R_P, R_T1, R_P, FIN_NONE, false},
-      {true, -1, S_CGR, 0, 0, 0, MASK_ACTIVE, FIN_CG, R_T1, R_NONE, R_P, FIN_NONE, false, true},
+      {true, -1, S_NORM, 1, 0, 0, MASK_RUN, FIN_ALPHA, R_P, R_T1, R_P, FIN_NONE, false, true},
+      {true, -1, S_CGR, 0, 0, 0, MASK_ACTIVE, FIN_CG, R_T1, R_NONE, R_P, FIN_ALPHA_ALL, false, true},
       {false, -1, BLAS_CGUPD, 0, 0, 0, MASK_ACTIVE, FIN_NONE, R_NONE, R_P, R_NONE, FIN_CG, false, true},
   };
   const Phase* k = op_ == OP_STAG ? st : eo_ ? eo : full;

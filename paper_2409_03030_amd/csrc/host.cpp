@@ -115,6 +115,26 @@ void tune_store(const wd_lattice_s* lat, int prec, int recon, int nrhs, Tune t) 
   g_tune[tkey(lat, prec, recon, nrhs)] = t;
 }
 
+// Staggered stencil shapes (one thread per site and rhs), filled by
+// wd_stag_autotune; without an entry the Wilson entry's block shape is used.
+static std::map<TuneKey, Tune> g_stag_tune;
+
+Tune stag_tune_lookup(const wd_lattice_s* lat, int prec, int recon, int nrhs) {
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_stag_tune.find(tkey(lat, prec, recon, nrhs));
+    if (it != g_stag_tune.end()) return it->second;
+  }
+  Tune t = tune_lookup(lat, prec, recon, nrhs);
+  t.split = 1;
+  return t;
+}
+
+void stag_tune_store(const wd_lattice_s* lat, int prec, int recon, int nrhs, Tune t) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_stag_tune[tkey(lat, prec, recon, nrhs)] = t;
+}
+
 // ---------------------------------------------------------------------------
 // launch assembly
 // ---------------------------------------------------------------------------

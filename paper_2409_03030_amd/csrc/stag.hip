@@ -3,8 +3,8 @@
 // deterministic two-stage reductions as the Wilson kernels; one thread per
 // (output site, rhs).  The CG runs on the even block
 // M_e = m^2 - H_eo H_oe (Hermitian positive definite):
-//   t = H_oe p ; <p, M_e p> = m^2 |p|^2 + |t|^2        S_NORM  (FIN_ALPHA)
-//   r -= alpha (m^2 p - H_eo t) ; |r|^2                S_CGR   (FIN_CG)
+//   t = H_oe p ; <p, M_e p> = m^2 |p|^2 + |t|^2        S_NORM  (alpha partials)
+//   alpha ; r -= alpha (m^2 p - H_eo t) ; |r|^2        S_CGR   (alpha folded in, FIN_CG)
 //   x += alpha p ; p = r + beta p                      sblas CGUPD
 #include "wd_kcommon.h"
 #include "wd_kernels.h"
@@ -17,7 +17,13 @@ __global__ void __launch_bounds__(kBlock) stag_kernel(const Launch L) {
   using T = typename RealOf<P>::T;
   const Tile t = make_tile(L);
   const Slot& S = L.s[t.slot];
-  if (L.prefin != FIN_NONE && t.lblk == 0) gather_and_finalize(L, S, L.prefin);
+  // alpha folded into every block (the residual update needs it everywhere);
+  // the mask then uses the block's own copy of `active`
+  __shared__ double s_alpha[kBlock / 2];
+  __shared__ int s_active[kBlock / 2];
+  const bool fold_alpha = MODE == S_CGR && L.prefin == FIN_ALPHA_ALL;
+  if (fold_alpha) fold_finalize_alpha(L, S, t, s_alpha, s_active);
+  else if (L.prefin != FIN_NONE && t.lblk == 0) gather_and_finalize(L, S, L.prefin);
   // Launches with a reduction run every block: every block partial of the
   // slot must be written for the finalize step.
   if (L.fin == FIN_NONE && !slot_selected(L, S)) return;
@@ -25,7 +31,7 @@ __global__ void __launch_bounds__(kBlock) stag_kernel(const Launch L) {
   const int par = t.parity;
   const size_t ne = (size_t)S.g.n * L.nrhs;
   const size_t e = (size_t)t.site * L.nrhs + t.rhs;
-  const bool sel = t.valid && rhs_selected(S.st, L.mask, t.rhs);
+  const bool sel = t.valid && (fold_alpha ? s_active[t.rhs] != 0 : rhs_selected(S.st, L.mask, t.rhs));
   double v = 0.0;
   if (sel) {
     const char* in = (const char*)S.in + (both ? (size_t)(1 - par) * S.vstride : 0);
@@ -62,7 +68,7 @@ __global__ void __launch_bounds__(kBlock) stag_kernel(const Launch L) {
         q.c[k].im = c * p.c[k].im - T(0.5) * h.c[k].im;
       }
       if (MODE == S_CGR) {
-        const T alpha = (T)S.st[t.rhs].alpha;
+        const T alpha = (T)(fold_alpha ? s_alpha[t.rhs] : S.st[t.rhs].alpha);
         char* r = (char*)S.r + (both ? (size_t)par * S.astride : 0);
         cvec<T> rv;
         SFmt<P>::load(r, ne, e, rv);

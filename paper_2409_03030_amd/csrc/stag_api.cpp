@@ -56,7 +56,7 @@ SLayout s_layout(wd_lattice_s* lat, const wd_solve_params& p, int nrhs) {
 wd_status stag64(wd_lattice_s* lat, int nrhs, int mode, int parity, const void* in, void* out, const void* aux,
                  RhsState* st, double coef, double coef2, size_t vb, hipStream_t s) {
   const int recon = lat->store[F64].recon;
-  const Tune t = tune_lookup(lat, F64, recon, nrhs);
+  const Tune t = stag_tune_lookup(lat, F64, recon, nrhs);
   Launch L = base_launch(nrhs, t, parity);
   L.nslots = 1;
   L.mask = MASK_NONE;
@@ -104,7 +104,7 @@ wd_status wd_stag_apply(wd_lattice lat, void* y, const void* x, int32_t nrhs, do
   char* vout = vin + 2 * vb;
   WD_HIP(launch_stag_import(x, vin, vb, lat->g, nrhs, 2, prec, st));
   const int recon = lat->store[prec].recon;
-  const Tune t = tune_lookup(lat, prec, recon, nrhs);
+  const Tune t = stag_tune_lookup(lat, prec, recon, nrhs);
   Launch L = base_launch(nrhs, t, 2);
   L.nslots = 1;
   L.mask = MASK_NONE;
@@ -121,6 +121,81 @@ wd_status wd_stag_apply(wd_lattice lat, void* y, const void* x, int32_t nrhs, do
   finish_launch(L);
   WD_HIP(launch_stag(L, prec, recon, S_XPAY, st));
   WD_HIP(launch_stag_export(vout, vb, y, lat->g, nrhs, 2, prec, st));
+  return WD_OK;
+}
+
+wd_status wd_stag_autotune(wd_lattice lat, int32_t prec, int32_t nrhs, void* ws, size_t ws_bytes,
+                           int32_t* best_sites_per_block, int32_t* best_swizzle, void* stream) {
+  if (!lat || !ws) return fail(WD_EINVAL, "null argument");
+  if (prec != F64 && prec != F32) return fail(WD_EINVAL, "the staggered operator runs at FP64 or FP32");
+  if (nrhs < 1 || nrhs > kBlock / 2) return fail(WD_EINVAL, "nrhs out of range");
+  if (!lat->store[prec].ptr) return fail(WD_ENOGAUGE, "no gauge store of precision %d registered", prec);
+  const size_t need = wd_stag_apply_workspace_bytes(lat, prec, nrhs);
+  if (ws_bytes < need) return fail(WD_EBUFSIZE, "workspace holds %zu bytes, %zu needed", ws_bytes, need);
+  hipStream_t st = (hipStream_t)stream;
+  const size_t vb = field_bytes(OP_STAG, prec, (size_t)lat->g.n, nrhs);
+  char* vin = (char*)ws;
+  char* vout = vin + 2 * vb;
+  // a deterministic input: the even block filled with a byte pattern of small values
+  std::vector<unsigned char> pat(vb);
+  for (size_t i = 0; i < vb; ++i) pat[i] = (unsigned char)((i * 2654435761u) >> 13) & 0x3f;
+  WD_HIP(hipMemcpyAsync(vin, pat.data(), vb, hipMemcpyHostToDevice, st));
+  WD_HIP(hipStreamSynchronize(st));
+  const int recon = lat->store[prec].recon;
+  std::vector<unsigned char> ref, got;
+  double best = 1e30;
+  Tune bt = stag_tune_lookup(lat, prec, recon, nrhs);
+  hipEvent_t e0, e1;
+  WD_HIP(hipEventCreate(&e0));
+  WD_HIP(hipEventCreate(&e1));
+  wd_status res = WD_OK;
+  // blocks of at least 128 threads: below that the per-block fixed costs of
+  // the CG kernels (the folded reductions) outweigh what the bare stencil gains
+  for (int sblk = 1; sblk <= kBlock && res == WD_OK; sblk *= 2) {
+    if (sblk * nrhs < kBlock / 2 || sblk * nrhs > kBlock) continue;
+    for (int swz = 0; swz <= 1 && res == WD_OK; ++swz) {
+      Launch L = base_launch(nrhs, Tune{sblk, swz, 1}, 1);
+      L.nslots = 1;
+      L.mask = MASK_NONE;
+      L.fin = FIN_NONE;
+      Slot& S = L.s[0];
+      fill_slot_geometry(S, lat, sblk, 1);
+      S.gauge = (const char*)lat->store[prec].ptr;
+      S.in = vin;
+      S.out = vout;
+      S.vstride = vb;
+      finish_launch(L);
+      hipError_t e = hipSuccess;
+      for (int i = 0; i < 2 && e == hipSuccess; ++i) e = launch_stag(L, prec, recon, S_PLAIN, st);
+      if (e == hipSuccess) e = hipEventRecord(e0, st);
+      for (int i = 0; i < 20 && e == hipSuccess; ++i) e = launch_stag(L, prec, recon, S_PLAIN, st);
+      if (e == hipSuccess) e = hipEventRecord(e1, st);
+      if (e == hipSuccess) e = hipEventSynchronize(e1);
+      float ms = 0.f;
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+      std::vector<unsigned char>& dst = ref.empty() ? ref : got;
+      dst.resize(vb);
+      if (e == hipSuccess) e = hipMemcpy(dst.data(), vout, vb, hipMemcpyDeviceToHost);
+      if (e != hipSuccess) {
+        res = hip_fail(e, "staggered autotune launch");
+        break;
+      }
+      if (&dst == &got && got != ref) {
+        res = fail(WD_EDEVICE, "staggered stencil output differs between launch shapes (sblk %d swz %d)", sblk, swz);
+        break;
+      }
+      if (ms < best) {
+        best = ms;
+        bt = Tune{sblk, swz, 1};
+      }
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (res != WD_OK) return res;
+  stag_tune_store(lat, prec, recon, nrhs, bt);
+  if (best_sites_per_block) *best_sites_per_block = bt.sblk;
+  if (best_swizzle) *best_swizzle = bt.swz;
   return WD_OK;
 }
 

@@ -55,6 +55,8 @@ struct Tune {
 bool valid_tune(const Tune& t, int nrhs, int prec);
 Tune tune_lookup(const wd_lattice_s* lat, int prec, int recon, int nrhs);
 void tune_store(const wd_lattice_s* lat, int prec, int recon, int nrhs, Tune t);
+Tune stag_tune_lookup(const wd_lattice_s* lat, int prec, int recon, int nrhs);
+void stag_tune_store(const wd_lattice_s* lat, int prec, int recon, int nrhs, Tune t);
 int default_sblk(int nrhs);
 
 // Slot of a launch for a lattice; blocks for `parity` (0/1 or 2 = both).

@@ -102,12 +102,13 @@ __device__ void finalize_rhs(int fin, RhsState& s, double sum) {
       else s.state = ST_RUN;
       break;
     }
-    case FIN_ALPHA: {  // sum = <p, A p> = ||D p||^2
+    case FIN_ALPHA:      // sum = <p, A p> = ||D p||^2
+    case FIN_ALPHA_ALL: {  // the same, without counting the iteration (see fold_finalize_alpha)
       if (s.state == ST_RUN) {
         if (finite_d(sum) && sum > 0.0) {
           s.alpha = s.rho / sum;
           s.active = 1;
-          s.iters += 1;
+          if (fin == FIN_ALPHA) s.iters += 1;
           s.rho_prev = s.rho;
         } else {
           s.alpha = 0.0;
@@ -266,6 +267,36 @@ __device__ void gather_and_finalize(const Launch& L, const Slot& S, int fin) {
   reduce_partials(S.partial, S.npart, L.nrhs, red);
   const int tid = (int)threadIdx.x;
   if (tid < L.nrhs && S.st != nullptr) finalize_rhs(fin, S.st[tid], red[tid]);
+  __syncthreads();
+}
+
+// Stage 2 of FIN_ALPHA run by every block of the stencil that needs alpha
+// (the staggered residual update): each block sums the same partials in the
+// same order and applies the alpha update to a private copy of the states;
+// the first block of the slot stores the states and counts the iteration.
+// Without the count the update reads only fields it leaves unchanged (rho,
+// the state of a running rhs) or sets idempotently (alpha, active, rho_prev,
+// a non-finite state), so a block that reads a state after the first block
+// stored it computes the same result.
+__device__ void fold_finalize_alpha(const Launch& L, const Slot& S, const Tile& t, double* alpha, int* active) {
+  __shared__ double red[kRedSlots];
+  reduce_partials(S.partial, S.npart, L.nrhs, red);
+  const int tid = (int)threadIdx.x;
+  if (tid < L.nrhs) {
+    RhsState s = S.st[tid];
+    const int iters = s.iters;
+    finalize_rhs(FIN_ALPHA_ALL, s, red[tid]);
+    alpha[tid] = s.alpha;
+    active[tid] = s.active;
+    if (t.lblk == 0) {
+      RhsState& d = S.st[tid];
+      d.alpha = s.alpha;
+      d.active = s.active;
+      d.rho_prev = s.rho_prev;
+      d.state = s.state;
+      d.iters = iters + (s.active ? 1 : 0);
+    }
+  }
   __syncthreads();
 }
 

@@ -42,7 +42,7 @@ enum State : int { ST_RUN = 0, ST_HOLD = 1, ST_DONE = 2, ST_NOTCONV = 3, ST_NONF
 enum Mask : int { MASK_NONE = 0, MASK_RUN = 1, MASK_HOLD = 2, MASK_RU = 3, MASK_ACTIVE = 4 };
 enum HopMode : int { HOP_PLAIN = 0, HOP_XPAY = 1, HOP_CGR = 2, HOP_RESID = 3 };
 enum BlasMode : int { BLAS_INIT = 0, BLAS_CGUPD = 1, BLAS_RU_ACC = 2, BLAS_RU_FIN = 3 };
-enum Fin : int { FIN_NONE = 0, FIN_ALPHA = 1, FIN_CG = 2, FIN_RESID = 3, FIN_INIT = 4 };
+enum Fin : int { FIN_NONE = 0, FIN_ALPHA = 1, FIN_CG = 2, FIN_RESID = 3, FIN_INIT = 4, FIN_ALPHA_ALL = 5 };
 
 struct Slot {
   Geom g;
@@ -77,7 +77,8 @@ struct Launch {
   int mask;             // Mask
   int fin;              // Fin
   int prefin;           // Fin of the previous launch's partials, run before this launch's own work: by block 0
-                        // of each slot in a stencil; by every block (FIN_CG only) in the CG vector update
+                        // of each slot in a stencil; by every block for FIN_CG (CG vector update) and
+                        // FIN_ALPHA_ALL (staggered residual update)
   int swz;              // 1: XCD-aware block order
   int total_blocks;
   double coef;          // epilogue coefficient when no RhsState is attached

@@ -112,6 +112,8 @@ _SIGS = [
     ("wd_ta_add", C.c_int32, [_P, _P, C.c_double, _P, _P]),
     ("wd_stag_apply_workspace_bytes", C.c_size_t, [_P, C.c_int32, C.c_int32]),
     ("wd_stag_apply", C.c_int32, [_P, _P, _P, C.c_int32, C.c_double, C.c_int32, C.c_int32, _P, C.c_size_t, _P]),
+    ("wd_stag_autotune", C.c_int32, [_P, C.c_int32, C.c_int32, _P, C.c_size_t, C.POINTER(C.c_int32),
+                                     C.POINTER(C.c_int32), _P]),
     ("wd_stag_solve_workspace_bytes", C.c_size_t, [_P, C.POINTER(SolveParams), C.c_int32]),
     ("wd_stag_solve", C.c_int32, [_P, _P, _P, C.c_int32, C.POINTER(C.c_double), C.c_int32, C.POINTER(SolveParams),
                                   _P, C.c_size_t, C.POINTER(SolveStats), _P]),
@@ -408,6 +410,16 @@ class Lattice:
         _check(lib().wd_stag_apply(self.handle, _ptr(y), _ptr(x), n, float(mass), int(bool(dagger)), PREC[prec],
                                    _ptr(ws), ws.numel(), _stream(stream)), "wd_stag_apply")
         return y
+
+    def stag_autotune(self, prec="f64", nrhs=1, stream=None):
+        """Tune the staggered stencil's launch shape; returns (sites per block, swizzle)."""
+        nb = int(lib().wd_stag_apply_workspace_bytes(self.handle, PREC[prec], nrhs))
+        dev = next(iter(self.stores.values())).device
+        ws = self._workspace(nb, dev, ("stag_apply", PREC[prec], nrhs))
+        sb, sw = C.c_int32(), C.c_int32()
+        _check(lib().wd_stag_autotune(self.handle, PREC[prec], nrhs, _ptr(ws), ws.numel(), C.byref(sb), C.byref(sw),
+                                      _stream(stream)), "wd_stag_autotune")
+        return sb.value, sw.value
 
     def stag_solve(self, b, mass, params=None, dagger=False, out=None, stream=None, check=True):
         """x with D x = b (or D^dag x = b) for the staggered operator, even-odd CG.

@@ -124,3 +124,24 @@ def test_full_size_solve():
         res = np.linalg.norm(b - S.apply_staggered(U, _host(x), 0.1, BC)) / np.linalg.norm(b)
         # the CG tolerance 1e-10 applies to M_e x_e = b'_e; |r_D| = |r_M| / m and |b'| <= 3 |b|
         assert res <= 5e-9, (inner, res)
+
+
+def test_autotune_then_solve():
+    """The staggered autotuner's shapes give the same stencil output; a solve
+    with the tuned shapes still meets the oracle's residual."""
+    W = _W()
+    L = (8, 4, 6, 8)
+    g = qcdgen.rng(104)
+    U = qcdgen.links_exp(L, 0.3, g)
+    lat = _lattice(L, U)
+    b = _field(L, g)
+    y0 = _host(lat.stag_apply(_dev(b), 0.2))
+    for prec in ("f64", "f32"):
+        sb, sw = lat.stag_autotune(prec, 1)
+        assert sb * 1 >= 64 and sw in (0, 1)
+    y1 = _host(lat.stag_apply(_dev(b), 0.2))
+    assert np.array_equal(y0, y1) or np.linalg.norm(y1 - y0) <= 1e-14 * np.linalg.norm(y0)
+    x, st = lat.stag_solve(_dev(b), 0.2, params=W.default_params(inner="f32", delta=1e-2))
+    assert st[0]["status"] == 0
+    res = np.linalg.norm(b - S.apply_staggered(U, _host(x), 0.2, BC)) / np.linalg.norm(b)
+    assert res <= 1e-9
