@@ -115,3 +115,51 @@ def test_dense_solve_and_spectrum():
     assert info["converged"]
     assert np.linalg.norm(x - x_ref) / np.linalg.norm(x_ref) < 1e-10
     assert S.residual_staggered(U, x, b, m, BC_AP) < 1e-11
+
+
+def test_staggered_free_propagator_and_pion():
+    """At U = 1, D^-1 = (m - H) / (m^2 - H^2) and m^2 - H^2 is the scalar
+    m^2 + sum sin^2 p on every plane wave, so the point propagator is (m - H)
+    applied to G(x) = (1/V) sum_p e^{ipx} / (m^2 + sum sin^2 p) (an inverse FFT,
+    with the antiperiodic twist in t)."""
+    L = (4, 4, 4, 6)
+    m = 0.2
+    U = qcdgen.links_unit(L)
+    Lt, Lz, Ly, Lx = qcdgen.site_shape(L)
+    shift = [0.5 if BC_AP[mu] == -1 else 0.0 for mu in range(4)]
+    n = np.indices((Lt, Lz, Ly, Lx))
+    p = [2 * np.pi * (n[3 - mu] + shift[mu]) / L[mu] for mu in range(4)]
+    lam = m * m + sum(np.sin(pm) ** 2 for pm in p)
+    Gs = np.fft.ifftn(1.0 / lam, axes=(0, 1, 2, 3))
+    twist = np.exp(1j * np.pi * sum(shift[mu] * 2 * n[3 - mu] / L[mu] for mu in range(4)))
+    Gs = Gs * twist
+    src = S.point_sources_staggered(L)
+    ref = np.empty_like(src)
+    for a in range(3):
+        g_a = np.zeros_like(src[a])
+        g_a[..., a] = Gs
+        ref[a] = S.apply_staggered_dag(U, g_a, m, BC_AP)
+    G, infos = S.staggered_point_propagator(U, m, BC_AP, src, tol=1e-13)
+    assert all(i["converged"] for i in infos)
+    assert np.linalg.norm(G - ref) / np.linalg.norm(ref) < 1e-10
+    C = S.staggered_pion_correlator(G)
+    assert np.all(C > 0)
+    for t in range(1, Lt):
+        assert C[t] == pytest.approx(C[Lt - t], rel=1e-10)
+    # a heavy quark: G ~ delta / m, C(0) ~ 3 / m^2
+    Gh, _ = S.staggered_point_propagator(U, 50.0, BC_AP, src)
+    assert S.staggered_pion_correlator(Gh)[0] == pytest.approx(3 / 50.0 ** 2, rel=1e-3)
+
+
+def test_staggered_pion_gauge_invariant():
+    L = (4, 4, 4, 4)
+    g = qcdgen.rng(95)
+    U = qcdgen.links_exp(L, 0.4, g)
+    Om = qcdgen.random_gauge_transform(L, g)
+    UO = np.empty_like(U)
+    for mu in range(4):
+        UO[mu] = np.einsum("...ab,...bc,...dc->...ad", Om, U[mu], np.conj(O.shift_forward(Om, mu)))
+    src = S.point_sources_staggered(L)
+    G1, _ = S.staggered_point_propagator(U, 0.2, BC_AP, src, tol=1e-13)
+    G2, _ = S.staggered_point_propagator(UO, 0.2, BC_AP, src, tol=1e-13)
+    assert np.allclose(S.staggered_pion_correlator(G1), S.staggered_pion_correlator(G2), rtol=1e-9, atol=0)
