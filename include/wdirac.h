@@ -289,6 +289,21 @@ wd_status wd_stag_solve(wd_lattice lat, void* x, const void* b, int32_t nrhs, co
                         const wd_solve_params* params, void* ws, size_t ws_bytes, wd_solve_stats* stats,
                         void* stream);
 
+/* Goldstone pion correlator of staggered quarks (the staggered entry of the
+ * paper's pion correlators, Sec. 2 and App. D):
+ *   corr[t] = sum over the spatial sites of time slice (t0 + t) mod Lt, over the
+ *             nsrc propagator columns and over colour, of |S|^2,
+ * for t = 0 .. Lt-1.  S (device, staggered layout [nsrc][t][z][y][x][colour 3]
+ * complex128) holds the solutions of D S_a = point source a, usually the 3
+ * colour sources at one site of slice t0; the staggered form of gamma5-
+ * hermiticity, G(y, x) = eps(x) eps(y) G(x, y)^dag with eps = (-1)^(x+y+z+t),
+ * turns the pion contraction into this sum of squared moduli.  Workspace:
+ * wd_pion_workspace_bytes.  FP64 sums in a fixed order (deterministic); corr
+ * is a host array of Lt doubles.  Blocks the host; errors as
+ * wd_pion_correlator. */
+wd_status wd_stag_pion_correlator(wd_lattice lat, double* corr, const void* S, int32_t nsrc, int32_t t0,
+                                  void* ws, size_t ws_bytes, void* stream);
+
 /* ---- batched solve over several lattices in one launch sequence ------- */
 
 typedef struct {

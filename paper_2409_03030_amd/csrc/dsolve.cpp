@@ -284,7 +284,7 @@ size_t wd_pion_workspace_bytes(wd_lattice lat) {
   return align_up((size_t)Lt * pion_shares(Lt) * sizeof(double)) + align_up((size_t)Lt * sizeof(double));
 }
 
-wd_status wd_pion_correlator(wd_lattice lat, double* corr, const void* S, int32_t nsrc, int32_t t0, void* ws,
+static wd_status pion_common(wd_lattice lat, double* corr, const void* S, int32_t nsrc, int32_t t0, int nc, void* ws,
                              size_t ws_bytes, void* stream) {
   if (!lat || !corr || !S || !ws) return fail(WD_EINVAL, "null argument");
   const int Lt = lat->L[3];
@@ -295,10 +295,20 @@ wd_status wd_pion_correlator(wd_lattice lat, double* corr, const void* S, int32_
   hipStream_t st = (hipStream_t)stream;
   double* partial = (double*)ws;
   double* dcorr = (double*)((char*)ws + align_up((size_t)Lt * pion_shares(Lt) * sizeof(double)));
-  WD_HIP(launch_pion(S, lat->g, nsrc, t0, partial, dcorr, st));
+  WD_HIP(launch_pion(S, lat->g, nsrc, t0, nc, partial, dcorr, st));
   WD_HIP(hipMemcpyAsync(corr, dcorr, (size_t)Lt * sizeof(double), hipMemcpyDeviceToHost, st));
   WD_HIP(hipStreamSynchronize(st));
   return WD_OK;
+}
+
+wd_status wd_pion_correlator(wd_lattice lat, double* corr, const void* S, int32_t nsrc, int32_t t0, void* ws,
+                             size_t ws_bytes, void* stream) {
+  return pion_common(lat, corr, S, nsrc, t0, 12, ws, ws_bytes, stream);
+}
+
+wd_status wd_stag_pion_correlator(wd_lattice lat, double* corr, const void* S, int32_t nsrc, int32_t t0, void* ws,
+                                  size_t ws_bytes, void* stream) {
+  return pion_common(lat, corr, S, nsrc, t0, 3, ws, ws_bytes, stream);
 }
 
 }  // extern "C"

@@ -30,18 +30,19 @@ hipError_t launch_gamma5_f64(void* v, size_t pstride, size_t ne, int parities, h
 }
 
 // Stage 1: block (t, j) of the grid sums |S|^2 over share j of the nb shares
-// of time slice (t0 + t) mod Lt.  A slice holds nsrc * V3 * 12 complex values
-// (V3 spatial sites per slice, source-major); share j is a contiguous range of
-// that sequence.  Threads stride through the share, then the block combines
+// of time slice (t0 + t) mod Lt.  A slice holds nsrc * V3 * nc complex values
+// (V3 spatial sites per slice, nc = 12 for Wilson spinors or 3 for staggered
+// colour vectors, source-major); share j is a contiguous range of that
+// sequence.  Threads stride through the share, then the block combines
 // its threads with wave butterflies and a fixed-order sum over the waves.
 __global__ void __launch_bounds__(256) pion_partial_kernel(const double2* __restrict__ S, long long V,
-                                                           long long V3, int Lt, int t0, int nsrc, int nb,
+                                                           long long V3, int Lt, int t0, int nsrc, int nb, int nc,
                                                            double* __restrict__ partial) {
   __shared__ double wsum[4];
   const int t = (int)blockIdx.x / nb;
   const int j = (int)blockIdx.x - t * nb;
   const int ts = (t0 + t) % Lt;
-  const long long per_src = V3 * 12;
+  const long long per_src = V3 * nc;
   const long long total = (long long)nsrc * per_src;
   const long long chunk = (total + nb - 1) / nb;
   const long long lo = (long long)j * chunk;
@@ -50,7 +51,7 @@ __global__ void __launch_bounds__(256) pion_partial_kernel(const double2* __rest
   for (long long i = lo + threadIdx.x; i < hi; i += blockDim.x) {
     const long long s = i / per_src;
     const long long k = i - s * per_src;
-    const double2 d = S[(s * V + (long long)ts * V3) * 12 + k];
+    const double2 d = S[(s * V + (long long)ts * V3) * nc + k];
     acc += d.x * d.x + d.y * d.y;
   }
 #pragma unroll
@@ -78,14 +79,14 @@ int pion_shares(int Lt) {
   return nb < 1 ? 1 : (nb > 256 ? 256 : nb);
 }
 
-hipError_t launch_pion(const void* S, const Geom& g, int nsrc, int t0, double* partial, double* corr,
+hipError_t launch_pion(const void* S, const Geom& g, int nsrc, int t0, int nc, double* partial, double* corr,
                        hipStream_t stream) {
   const int Lt = g.L[3];
   const long long V = 2LL * g.n;
   const long long V3 = V / Lt;
   const int nb = pion_shares(Lt);
   hipLaunchKernelGGL(pion_partial_kernel, dim3((unsigned)(Lt * nb)), dim3(256), 0, stream, (const double2*)S, V, V3,
-                     Lt, t0, nsrc, nb, partial);
+                     Lt, t0, nsrc, nb, nc, partial);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(pion_final_kernel, dim3((unsigned)((Lt + 63) / 64)), dim3(64), 0, stream, partial, Lt, nb, corr);

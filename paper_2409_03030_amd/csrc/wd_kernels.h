@@ -42,10 +42,11 @@ hipError_t launch_spinor_export(const void* src, size_t pstride, void* dst, cons
 // elements each.
 hipError_t launch_gamma5_f64(void* v, size_t pstride, size_t ne, int parities, hipStream_t stream);
 
-// Pion correlator of nsrc propagator columns S (complex128 boundary layout):
-// block partials (Lt * pion_shares(Lt) doubles) then corr[Lt] (device).
+// Pion correlator of nsrc propagator columns S (complex128 boundary layout,
+// nc complex values per site: 12 Wilson, 3 staggered): block partials
+// (Lt * pion_shares(Lt) doubles) then corr[Lt] (device).
 int pion_shares(int Lt);
-hipError_t launch_pion(const void* S, const Geom& g, int nsrc, int t0, double* partial, double* corr,
+hipError_t launch_pion(const void* S, const Geom& g, int nsrc, int t0, int nc, double* partial, double* corr,
                        hipStream_t stream);
 
 // Streaming read of `bytes` (a multiple of 16) by `blocks` blocks of 256

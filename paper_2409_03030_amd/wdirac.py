@@ -105,6 +105,8 @@ _SIGS = [
                                C.c_size_t, C.POINTER(SolveStats), _P]),
     ("wd_pion_workspace_bytes", C.c_size_t, [_P]),
     ("wd_pion_correlator", C.c_int32, [_P, C.POINTER(C.c_double), _P, C.c_int32, C.c_int32, _P, C.c_size_t, _P]),
+    ("wd_stag_pion_correlator", C.c_int32, [_P, C.POINTER(C.c_double), _P, C.c_int32, C.c_int32, _P, C.c_size_t,
+                                            _P]),
     ("wd_pseudofermion_heatbath", C.c_int32, [_P, _P, _P, C.c_double, _P, C.c_size_t, _P]),
     ("wd_fermion_force_workspace_bytes", C.c_size_t, [_P, C.POINTER(SolveParams)]),
     ("wd_fermion_force", C.c_int32, [_P, _P, C.POINTER(C.c_double), _P, C.c_double, C.POINTER(SolveParams), _P,
@@ -353,6 +355,31 @@ class Lattice:
         out = (C.c_double * Lt)()
         _check(lib().wd_pion_correlator(self.handle, out, _ptr(S), int(S.shape[0]), int(t0), _ptr(ws), ws.numel(),
                                         _stream(stream)), "wd_pion_correlator")
+        return np.array(out[:], dtype=np.float64)
+
+    def stag_propagator(self, mass, params=None, origin=(0, 0, 0, 0), stream=None, device="cuda"):
+        """The 3 colour point-source solutions G[a] of D G = delta_{x,origin} e_a
+        (staggered); returns (G, [stats dict per colour])."""
+        torch = _torch()
+        src = torch.zeros((3,) + self._stag_shape(None), dtype=torch.complex128, device=device)
+        x, y, z, t = origin
+        for a in range(3):
+            src[a, t, z, y, x, a] = 1.0
+        return self.stag_solve(src, mass, params=params, stream=stream)
+
+    def stag_pion_correlator(self, G, t0=0, stream=None):
+        """Goldstone pion correlator of staggered propagator columns G
+        [nsrc, Lt, Lz, Ly, Lx, 3]: C(t) = sum of |G|^2 over slice (t0 + t) mod Lt."""
+        import numpy as np
+        if G.dim() != 6 or tuple(G.shape[1:]) != self._stag_shape(None):
+            raise ValueError(f"G must be [nsrc, {self._stag_shape(None)}]")
+        _check_field(G, tuple(G.shape), "G")
+        nb = int(lib().wd_pion_workspace_bytes(self.handle))
+        ws = self._workspace(nb, G.device, ("pion",))
+        Lt = self.L[3]
+        out = (C.c_double * Lt)()
+        _check(lib().wd_stag_pion_correlator(self.handle, out, _ptr(G), int(G.shape[0]), int(t0), _ptr(ws),
+                                             ws.numel(), _stream(stream)), "wd_stag_pion_correlator")
         return np.array(out[:], dtype=np.float64)
 
     def pseudofermion(self, xi, kappa, out=None, stream=None):

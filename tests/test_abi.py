@@ -134,6 +134,12 @@ def test_staggered_argument_checks():
     assert lib.wd_stag_solve(h, dummy, dummy, 1, m, 0, C.byref(p16), dummy, big, stats, None) == W.WD_EINVAL
     assert lib.wd_stag_solve(h, dummy, dummy, 1, zero, 0, C.byref(p), dummy, big, stats, None) in (W.WD_EINVAL,
                                                                                                   W.WD_ENOGAUGE)
+    nw = lib.wd_pion_workspace_bytes(h)
+    corr = (C.c_double * 4)()
+    assert lib.wd_stag_pion_correlator(h, corr, dummy, 3, 4, dummy, nw, None) == W.WD_EINVAL   # t0 = Lt
+    assert lib.wd_stag_pion_correlator(h, corr, dummy, 0, 0, dummy, nw, None) == W.WD_EINVAL
+    assert lib.wd_stag_pion_correlator(h, corr, dummy, 3, 0, dummy, nw - 1, None) == W.WD_EBUFSIZE
+    assert lib.wd_stag_pion_correlator(h, corr, None, 3, 0, dummy, nw, None) == W.WD_EINVAL
     n1 = lib.wd_stag_solve_workspace_bytes(h, C.byref(p), 1)
     # a colour vector is a quarter of a Wilson spinor
     assert 0 < n1 < lib.wd_solver_workspace_bytes(h, C.byref(p), 1) + 4 ** 4 * 200

@@ -5,6 +5,9 @@
   wave, so D^dag D e^{ipx} c = (m^2 + sum_mu sin^2 p_mu) e^{ipx} c for every
   momentum allowed by the boundary signs.  A wrong phase, a missing 1/2 or a
   wrong boundary sign breaks it.
+* The point propagator at U = 1 against the closed form of the test helpers
+  (their own phases and shifts), the pion correlator's time reflection there,
+  the heavy-quark limit and gauge invariance.
 * The phases at hard-coded sites, anti-Hermiticity of the hopping part,
   gauge covariance, the even/odd structure, the dense solve and the spectrum
   (real part m) on a 2^4 lattice.
@@ -17,6 +20,7 @@ import pytest
 
 import oracle as O
 import qcdgen
+from closed_forms import free_staggered_point_propagator
 from oracle import staggered as S
 
 BC_AP = (1, 1, 1, -1)
@@ -118,30 +122,22 @@ def test_dense_solve_and_spectrum():
 
 
 def test_staggered_free_propagator_and_pion():
-    """At U = 1, D^-1 = (m - H) / (m^2 - H^2) and m^2 - H^2 is the scalar
-    m^2 + sum sin^2 p on every plane wave, so the point propagator is (m - H)
-    applied to G(x) = (1/V) sum_p e^{ipx} / (m^2 + sum sin^2 p) (an inverse FFT,
-    with the antiperiodic twist in t)."""
-    L = (4, 4, 4, 6)
+    """At U = 1 the point propagator is the closed form (m - H) G with the scalar
+    G(x) = (1/V) sum_p e^{ipx} / (m^2 + sum sin^2 p) (an inverse FFT, with the
+    antiperiodic twist in t), written in the test helpers with their own phases
+    and shifts; on a second lattice every direction but y is antiperiodic."""
     m = 0.2
+    for L, bc in (((4, 4, 4, 6), BC_AP), ((4, 2, 6, 4), (-1, 1, -1, -1))):
+        U = qcdgen.links_unit(L)
+        G, infos = S.staggered_point_propagator(U, m, bc, S.point_sources_staggered(L), tol=1e-13)
+        assert all(i["converged"] for i in infos)
+        ref = free_staggered_point_propagator(L, m, bc)
+        assert np.linalg.norm(G - ref) / np.linalg.norm(ref) < 1e-10, bc
+    L = (4, 4, 4, 6)
     U = qcdgen.links_unit(L)
-    Lt, Lz, Ly, Lx = qcdgen.site_shape(L)
-    shift = [0.5 if BC_AP[mu] == -1 else 0.0 for mu in range(4)]
-    n = np.indices((Lt, Lz, Ly, Lx))
-    p = [2 * np.pi * (n[3 - mu] + shift[mu]) / L[mu] for mu in range(4)]
-    lam = m * m + sum(np.sin(pm) ** 2 for pm in p)
-    Gs = np.fft.ifftn(1.0 / lam, axes=(0, 1, 2, 3))
-    twist = np.exp(1j * np.pi * sum(shift[mu] * 2 * n[3 - mu] / L[mu] for mu in range(4)))
-    Gs = Gs * twist
+    Lt = L[3]
     src = S.point_sources_staggered(L)
-    ref = np.empty_like(src)
-    for a in range(3):
-        g_a = np.zeros_like(src[a])
-        g_a[..., a] = Gs
-        ref[a] = S.apply_staggered_dag(U, g_a, m, BC_AP)
     G, infos = S.staggered_point_propagator(U, m, BC_AP, src, tol=1e-13)
-    assert all(i["converged"] for i in infos)
-    assert np.linalg.norm(G - ref) / np.linalg.norm(ref) < 1e-10
     C = S.staggered_pion_correlator(G)
     assert np.all(C > 0)
     for t in range(1, Lt):
