@@ -24,12 +24,17 @@ __global__ void __launch_bounds__(D == 8 ? kMaxBlock : kBlock) hop_kernel(const 
   using T = typename RealOf<P>::T;
   constexpr int A = AccOf<P>::value;
   using TA = typename RealOf<A>::T;
-  const Tile t = make_tile(L);
+  // The previous launch's reduction is finished by nslots extra workgroups at
+  // the start of the grid, one per slot, while the others run the stencil:
+  // this launch's own work must not depend on it (its mask reads only states
+  // that the finalize step leaves unchanged for the selected rhs).
+  const int lead = L.prefin != FIN_NONE ? L.nslots : 0;
+  if ((int)blockIdx.x < lead) {
+    gather_and_finalize(L, L.s[blockIdx.x], L.prefin);
+    return;
+  }
+  const Tile t = make_tile(L, lead);
   const Slot& S = L.s[t.slot];
-  // The previous launch's reduction is finished by the first block of each
-  // slot; this launch's own work must not depend on it (its mask reads only
-  // states that the finalize step leaves unchanged for the selected rhs).
-  if (L.prefin != FIN_NONE && t.lblk == 0) gather_and_finalize(L, S, L.prefin);
   // Launches with a reduction run every block: every block partial of the
   // slot must be written for the finalize step.
   if (L.fin == FIN_NONE && !slot_selected(L, S)) return;
@@ -122,7 +127,8 @@ __global__ void __launch_bounds__(D == 8 ? kMaxBlock : kBlock) hop_kernel(const 
 
 template <int P, int R, int MODE, int D>
 static hipError_t launch_one(const Launch& L, hipStream_t stream) {
-  dim3 grid((unsigned)L.total_blocks), block((unsigned)(D * L.sblk * L.nrhs));
+  const int lead = L.prefin != FIN_NONE ? L.nslots : 0;  // finalize-only workgroups
+  dim3 grid((unsigned)(L.total_blocks + lead)), block((unsigned)(D * L.sblk * L.nrhs));
   hipLaunchKernelGGL((hop_kernel<P, R, MODE, D>), grid, block, 0, stream, L);
   return hipGetLastError();
 }

@@ -28,9 +28,11 @@ __device__ __forceinline__ int logical_block(int w, int nb, int swz) {
   return start + (w >> 3);
 }
 
-__device__ __forceinline__ Tile make_tile(const Launch& L) {
+// lead: workgroups at the start of the grid that take no tile (they finish the
+// previous launch's reduction).
+__device__ __forceinline__ Tile make_tile(const Launch& L, int lead = 0) {
   Tile t;
-  const int b = logical_block((int)blockIdx.x, L.total_blocks, L.swz);
+  const int b = logical_block((int)blockIdx.x - lead, L.total_blocks, L.swz);
   int sl = 0;
 #pragma unroll 1
   for (int i = 1; i < L.nslots; ++i)

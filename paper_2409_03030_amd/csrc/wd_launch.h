@@ -76,9 +76,10 @@ struct Launch {
   int g5in, g5out;
   int mask;             // Mask
   int fin;              // Fin
-  int prefin;           // Fin of the previous launch's partials, run before this launch's own work: by block 0
-                        // of each slot in a stencil; by every block for FIN_CG (CG vector update) and
-                        // FIN_ALPHA_ALL (staggered residual update)
+  int prefin;           // Fin of the previous launch's partials, run alongside or before this launch's own
+                        // work: by one extra workgroup per slot at the start of a Wilson stencil's grid, by
+                        // block 0 of each slot in a staggered stencil, by every block for FIN_CG (CG vector
+                        // update) and FIN_ALPHA_ALL (staggered residual update)
   int swz;              // 1: XCD-aware block order
   int total_blocks;
   double coef;          // epilogue coefficient when no RhsState is attached

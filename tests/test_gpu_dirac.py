@@ -217,11 +217,13 @@ def test_launch_shapes_match_oracle(nrhs, split, sblk, swz):
         for r in range(nrhs):
             assert _rel(y[r], O.apply_Dhat(U, psi[r] * e, 0.1365, BC)) < TOL[prec]
             assert _rel(yd[r], O.apply_Ahat(U, psi[r] * e, 0.1365, BC)) < 2 * TOL[prec]
-    # and a solve through the same shapes
+    # and solves through the same shapes (every reducing epilogue: the norms
+    # of the CG at each inner precision and of the FP64 reliable updates)
     b = np.ascontiguousarray(psi[0])
-    x, st = lat.solve(_dev(b), 0.1365, W.default_params(inner="f16", delta=1e-2))
-    assert st[0]["status"] == 0
-    assert O.residual_DdagD(U, _host(x), b, 0.1365, BC, True) <= 1e-10
+    for inner in ("f64", "f32", "f16"):
+        x, st = lat.solve(_dev(b), 0.1365, W.default_params(inner=inner, delta=1e-2 if inner != "f64" else 0.0))
+        assert st[0]["status"] == 0, inner
+        assert O.residual_DdagD(U, _host(x), b, 0.1365, BC, True) <= 1e-10, inner
 
 
 def test_time_hop_modes():
