@@ -43,6 +43,23 @@ template <typename T> WD_HD cplx<T> ctimes_mi(cplx<T> a) { return {a.im, -a.re};
 template <typename T> WD_HD cplx<T> cconj(cplx<T> a) { return {a.re, -a.im}; }
 template <typename T> WD_HD cplx<T> cscale(cplx<T> a, T s) { return {a.re * s, a.im * s}; }
 
+// A complex as a pair of halves (re, im), for the FP16 stencil.
+typedef _Float16 wd_h2 __attribute__((ext_vector_type(2)));
+typedef __fp16 wd_hp2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ wd_h2 cadd(wd_h2 a, wd_h2 b) { return a + b; }
+__device__ __forceinline__ wd_h2 csub(wd_h2 a, wd_h2 b) { return a - b; }
+__device__ __forceinline__ wd_h2 cadd_i(wd_h2 a, wd_h2 b) { return a + (wd_h2){-b.y, b.x}; }  // a + i b
+__device__ __forceinline__ wd_h2 csub_i(wd_h2 a, wd_h2 b) { return a + (wd_h2){b.y, -b.x}; }  // a - i b
+__device__ __forceinline__ wd_h2 h2_conj(wd_h2 v) {
+  return __builtin_bit_cast(wd_h2, __builtin_bit_cast(uint32_t, v) ^ 0x80000000u);
+}
+__device__ __forceinline__ wd_h2 h2_swap(wd_h2 v) { return v.yx; }
+__device__ __forceinline__ wd_h2 h2_bits(uint32_t u) { return __builtin_bit_cast(wd_h2, u); }
+__device__ __forceinline__ float dot2h(wd_h2 a, wd_h2 b, float c) {
+  return __builtin_amdgcn_fdot2(__builtin_bit_cast(wd_hp2, a), __builtin_bit_cast(wd_hp2, b), c, false);
+}
+
 // A full spinor: 4 spins x 3 colours; component k = 3*spin + colour.
 template <typename T> struct spinor { cplx<T> c[12]; };
 // A half spinor after spin projection: 2 spins x 3 colours.
@@ -343,22 +360,45 @@ WD_HD int neighbour_cb(const Geom& g, const Coord& k, int mu, int dir) {
 // The colour product commutes with the spin projection, so only h is
 // multiplied by the link and the lower spins are rebuilt afterwards.
 // ---------------------------------------------------------------------------
-template <int MU, int DIR, typename T>
-WD_HD void project(const spinor<T>& p, half_spinor<T>& h) {
+// The 4 spin components s0..s3 (colour a) of p map to the 2 of h; C is a
+// complex type with cadd/csub/cadd_i/csub_i (cplx<T>, or a pair of halves).
+template <int MU, int DIR, typename C>
+WD_HD void project_c(const C* p, C* h) {
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
-    cplx<T> s0 = p.c[a], s1 = p.c[3 + a], s2 = p.c[6 + a], s3 = p.c[9 + a];
+    C s0 = p[a], s1 = p[3 + a], s2 = p[6 + a], s3 = p[9 + a];
     if (DIR > 0) {  // 1 - g_mu
-      if (MU == 0) { h.c[a] = cadd_i(s0, s3); h.c[3 + a] = cadd_i(s1, s2); }
-      if (MU == 1) { h.c[a] = cadd(s0, s3);   h.c[3 + a] = csub(s1, s2); }
-      if (MU == 2) { h.c[a] = cadd_i(s0, s2); h.c[3 + a] = csub_i(s1, s3); }
-      if (MU == 3) { h.c[a] = csub(s0, s2);   h.c[3 + a] = csub(s1, s3); }
+      if (MU == 0) { h[a] = cadd_i(s0, s3); h[3 + a] = cadd_i(s1, s2); }
+      if (MU == 1) { h[a] = cadd(s0, s3);   h[3 + a] = csub(s1, s2); }
+      if (MU == 2) { h[a] = cadd_i(s0, s2); h[3 + a] = csub_i(s1, s3); }
+      if (MU == 3) { h[a] = csub(s0, s2);   h[3 + a] = csub(s1, s3); }
     } else {        // 1 + g_mu
-      if (MU == 0) { h.c[a] = csub_i(s0, s3); h.c[3 + a] = csub_i(s1, s2); }
-      if (MU == 1) { h.c[a] = csub(s0, s3);   h.c[3 + a] = cadd(s1, s2); }
-      if (MU == 2) { h.c[a] = csub_i(s0, s2); h.c[3 + a] = cadd_i(s1, s3); }
-      if (MU == 3) { h.c[a] = cadd(s0, s2);   h.c[3 + a] = cadd(s1, s3); }
+      if (MU == 0) { h[a] = csub_i(s0, s3); h[3 + a] = csub_i(s1, s2); }
+      if (MU == 1) { h[a] = csub(s0, s3);   h[3 + a] = cadd(s1, s2); }
+      if (MU == 2) { h[a] = csub_i(s0, s2); h[3 + a] = cadd_i(s1, s3); }
+      if (MU == 3) { h[a] = cadd(s0, s2);   h[3 + a] = cadd(s1, s3); }
     }
+  }
+}
+
+template <int MU, int DIR, typename T>
+WD_HD void project(const spinor<T>& p, half_spinor<T>& h) {
+  project_c<MU, DIR>(p.c, h.c);
+}
+
+// Lower spin components of the rebuilt spinor from the upper ones g0, g1.
+template <int MU, int DIR, typename T>
+WD_HD void lower_from_upper(cplx<T> g0, cplx<T> g1, cplx<T>& l2, cplx<T>& l3) {
+  if (DIR > 0) {  // lower = -A^dag g
+    if (MU == 0) { l2 = ctimes_mi(g1); l3 = ctimes_mi(g0); }
+    if (MU == 1) { l2 = cneg(g1);      l3 = g0; }
+    if (MU == 2) { l2 = ctimes_mi(g0); l3 = ctimes_i(g1); }
+    if (MU == 3) { l2 = cneg(g0);      l3 = cneg(g1); }
+  } else {        // lower = +A^dag g
+    if (MU == 0) { l2 = ctimes_i(g1);  l3 = ctimes_i(g0); }
+    if (MU == 1) { l2 = g1;            l3 = cneg(g0); }
+    if (MU == 2) { l2 = ctimes_i(g0);  l3 = ctimes_mi(g1); }
+    if (MU == 3) { l2 = g0;            l3 = g1; }
   }
 }
 
@@ -371,19 +411,24 @@ WD_HD void accumulate(spinor<T>& acc, const half_spinor<T>& g) {
     acc.c[a] = cadd(acc.c[a], g0);
     acc.c[3 + a] = cadd(acc.c[3 + a], g1);
     cplx<T> l2, l3;
-    if (DIR > 0) {  // lower = -A^dag g
-      if (MU == 0) { l2 = ctimes_mi(g1); l3 = ctimes_mi(g0); }
-      if (MU == 1) { l2 = cneg(g1);      l3 = g0; }
-      if (MU == 2) { l2 = ctimes_mi(g0); l3 = ctimes_i(g1); }
-      if (MU == 3) { l2 = cneg(g0);      l3 = cneg(g1); }
-    } else {        // lower = +A^dag g
-      if (MU == 0) { l2 = ctimes_i(g1);  l3 = ctimes_i(g0); }
-      if (MU == 1) { l2 = g1;            l3 = cneg(g0); }
-      if (MU == 2) { l2 = ctimes_i(g0);  l3 = ctimes_mi(g1); }
-      if (MU == 3) { l2 = g0;            l3 = g1; }
-    }
+    lower_from_upper<MU, DIR>(g0, g1, l2, l3);
     acc.c[6 + a] = cadd(acc.c[6 + a], l2);
     acc.c[9 + a] = cadd(acc.c[9 + a], l3);
+  }
+}
+
+// acc += w * (full spinor rebuilt from g), one FMA per real.
+template <int MU, int DIR>
+WD_HD void accumulate_scaled(spinor<float>& acc, const half_spinor<float>& g, float w) {
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    cplx<float> g0 = g.c[a], g1 = g.c[3 + a];
+    cplx<float> l2, l3;
+    lower_from_upper<MU, DIR>(g0, g1, l2, l3);
+    acc.c[a] = {fmaf(w, g0.re, acc.c[a].re), fmaf(w, g0.im, acc.c[a].im)};
+    acc.c[3 + a] = {fmaf(w, g1.re, acc.c[3 + a].re), fmaf(w, g1.im, acc.c[3 + a].im)};
+    acc.c[6 + a] = {fmaf(w, l2.re, acc.c[6 + a].re), fmaf(w, l2.im, acc.c[6 + a].im)};
+    acc.c[9 + a] = {fmaf(w, l3.re, acc.c[9 + a].re), fmaf(w, l3.im, acc.c[9 + a].im)};
   }
 }
 
@@ -528,6 +573,126 @@ WD_HD void hop_finish(HopBuf<P>& b, bool g5in, spinor<typename RealOf<P>::T>& ac
   accumulate<MU, DIR>(acc, gh);
 }
 
+// ---------------------------------------------------------------------------
+// FP16 hops in packed half arithmetic.  The neighbour spinor stays in its
+// stored halves (component / site scale): the spin projection adds pairs of
+// halves (one v_pk_add_f16 per complex), the colour product takes dot
+// products of half pairs with FP32 accumulation (v_dot2_f32_f16; the half
+// products are exact in FP32), and the neighbour's scale, with the boundary
+// sign, multiplies the FP32 product as it is accumulated (one FMA per real).
+// Links are used as stored; the third row of a 12-real link is rebuilt in
+// FP32 and rounded to halves like the stored rows.  A complex is a pair of
+// halves (re, im):
+//   Re(U h) = sum dot2((U.re, -U.im), h)       Im(U h) = sum dot2(U, (h.im, h.re))
+//   Re(U^dag h) = sum dot2(U, h)               Im(U^dag h) = sum dot2((U.re, -U.im), (h.im, h.re))
+// ---------------------------------------------------------------------------
+struct HopBuf16 {
+  wd_h2 s[12];  // neighbour spinor as stored (component / scale)
+  float w;      // its scale
+  wd_h2 u[9];   // link as stored (12-real links: rows 0 and 1)
+  bool flip;    // the hop crosses a boundary with sign -1
+};
+
+template <int R, int H>
+__device__ __forceinline__ void hop_fetch16(const Geom& g, const Coord& k, int parity, int s, int rhs, int nrhs,
+                                            const char* gauge, const void* in, const float bc[4], HopBuf16& b) {
+  constexpr int MU = H >> 1;
+  constexpr int DIR = (H & 1) ? -1 : 1;
+  const size_t n = (size_t)g.n;
+  const size_t ne = n * (size_t)nrhs;
+  const int nb = neighbour_cb(g, k, MU, DIR);
+  const size_t e = (size_t)nb * nrhs + rhs;
+  const uint4* v = (const uint4*)in;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const uint4 d = v[c * ne + e];
+    b.s[4 * c] = h2_bits(d.x);
+    b.s[4 * c + 1] = h2_bits(d.y);
+    b.s[4 * c + 2] = h2_bits(d.z);
+    b.s[4 * c + 3] = h2_bits(d.w);
+  }
+  b.w = ((const float*)((const char*)in + SpinorFmt<F16>::data_bytes(ne)))[e];
+  // forward: U_mu(x), rooted at the output site (parity `parity`);
+  // backward: U_mu(x - mu), rooted at the neighbour (other parity).
+  const int lp = DIR > 0 ? parity : 1 - parity;
+  const size_t ls = DIR > 0 ? (size_t)s : (size_t)nb;
+  const char* lbase = gauge + (size_t)(lp * 4 + MU) * link_dir_bytes<F16, R>(n);
+  if constexpr (R == 12) {
+    const uint4 d = ((const uint4*)lbase)[ls];
+    const uint2 f = ((const uint2*)(lbase + 16 * n))[ls];
+    b.u[0] = h2_bits(d.x);
+    b.u[1] = h2_bits(d.y);
+    b.u[2] = h2_bits(d.z);
+    b.u[3] = h2_bits(d.w);
+    b.u[4] = h2_bits(f.x);
+    b.u[5] = h2_bits(f.y);
+  } else {
+    const uint32_t* lv = (const uint32_t*)lbase;
+#pragma unroll
+    for (int q = 0; q < 9; ++q) b.u[q] = h2_bits(lv[q * n + ls]);
+  }
+  const bool crosses = DIR > 0 ? (k.c[MU] == g.L[MU] - 1) : (k.c[MU] == 0);
+  b.flip = crosses && bc[MU] < 0.f;
+}
+
+template <int R, int H>
+__device__ __forceinline__ void hop_finish16(HopBuf16& b, bool g5in, spinor<float>& acc) {
+  constexpr int MU = H >> 1;
+  constexpr int DIR = (H & 1) ? -1 : 1;
+  wd_h2 uc[9];  // (U.re, -U.im)
+  if constexpr (R == 12) {
+    su3<float> f;
+#pragma unroll
+    for (int q = 0; q < 6; ++q) f.e[q] = {(float)b.u[q].x, (float)b.u[q].y};
+    reconstruct_row2(f);
+#pragma unroll
+    for (int q = 6; q < 9; ++q) b.u[q] = (wd_h2){(_Float16)f.e[q].re, (_Float16)f.e[q].im};
+  }
+#pragma unroll
+  for (int q = 0; q < 9; ++q) uc[q] = h2_conj(b.u[q]);
+  if (g5in) {
+#pragma unroll
+    for (int q = 6; q < 12; ++q) b.s[q] = -b.s[q];
+  }
+  wd_h2 h[6], hs[6];
+  project_c<MU, DIR>(b.s, h);
+#pragma unroll
+  for (int j = 0; j < 6; ++j) hs[j] = h2_swap(h[j]);
+  half_spinor<float> gh;
+#pragma unroll
+  for (int sp = 0; sp < 2; ++sp) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      float re = 0.f, im = 0.f;
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        if (DIR > 0) {  // U h: U_aj
+          re = dot2h(uc[3 * a + j], h[3 * sp + j], re);
+          im = dot2h(b.u[3 * a + j], hs[3 * sp + j], im);
+        } else {        // U^dag h: conj(U_ja)
+          re = dot2h(b.u[3 * j + a], h[3 * sp + j], re);
+          im = dot2h(uc[3 * j + a], hs[3 * sp + j], im);
+        }
+      }
+      gh.c[3 * sp + a] = {re, im};
+    }
+  }
+  accumulate_scaled<MU, DIR>(acc, gh, b.flip ? -b.w : b.w);
+}
+
+template <int R, int H0, int... J>
+__device__ __forceinline__ void hop_fetch_group16(std::integer_sequence<int, J...>, const Geom& g, const Coord& k,
+                                                  int parity, int s, int rhs, int nrhs, const char* gauge,
+                                                  const void* in, const float bc[4], HopBuf16* b) {
+  (hop_fetch16<R, H0 + J>(g, k, parity, s, rhs, nrhs, gauge, in, bc, b[J]), ...);
+}
+
+template <int R, int H0, int... J>
+__device__ __forceinline__ void hop_finish_group16(std::integer_sequence<int, J...>, HopBuf16* b, bool g5in,
+                                                   spinor<float>& acc) {
+  (hop_finish16<R, H0 + J>(b[J], g5in, acc), ...);
+}
+
 template <int P, int R, int H0, int... J>
 WD_HD void hop_fetch_group(std::integer_sequence<int, J...>, const Geom& g, const Coord& k, int parity, int s,
                            int rhs, int nrhs, const char* gauge, const void* in, const float bc[4], HopBuf<P>* b) {
@@ -551,9 +716,9 @@ WD_HD void hop_range(const Geom& g, const Coord& k, int parity, int s, int rhs, 
     hop_range<P, R, H0 + 1, NH - 1>(g, k, parity, s, rhs, nrhs, gauge, in, bc, g5in, acc);
   } else if constexpr (NH > 0) {
     constexpr int M = NH < 4 ? NH : 4;
-    HopBuf<P> b[M];
-    hop_fetch_group<P, R, H0>(std::make_integer_sequence<int, M>{}, g, k, parity, s, rhs, nrhs, gauge, in, bc, b);
-    hop_finish_group<P, H0>(std::make_integer_sequence<int, M>{}, b, g5in, acc);
+    HopBuf16 b[M];
+    hop_fetch_group16<R, H0>(std::make_integer_sequence<int, M>{}, g, k, parity, s, rhs, nrhs, gauge, in, bc, b);
+    hop_finish_group16<R, H0>(std::make_integer_sequence<int, M>{}, b, g5in, acc);
     hop_range<P, R, H0 + M, NH - M>(g, k, parity, s, rhs, nrhs, gauge, in, bc, g5in, acc);
   }
 }
