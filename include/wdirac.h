@@ -346,7 +346,10 @@ wd_status wd_time_read(const void* buf, size_t bytes, int32_t n, void* out, size
 
 /* Autotune the stencil launch shape (sites per workgroup, XCD-aware block
  * order, number of threads the 8 hops of a site are split over) for this
- * lattice, precision and nrhs by timing every candidate on stream; the choice
+ * lattice, precision and nrhs by timing every candidate on stream.  Of the
+ * candidates within 3 % of the fastest, the one with the fewest workgroups is
+ * chosen (each reducing launch of the CG leaves one partial sum per workgroup
+ * for stage 2 to gather).  The choice
  * is kept in a process-wide table keyed by (dims, prec, recon, nrhs) and used
  * by every later launch.  Candidates with the same split must produce
  * bit-identical output (checked).  Needs wd_apply_workspace_bytes(lat, prec,
