@@ -639,8 +639,8 @@ def bench_staggered(args):
     lat = W.Lattice(L, BC)
     for prec in ("f64", "f32"):
         lat.set_gauge(Ud, prec, 12)
-        sb, sw = lat.stag_autotune(prec, 1)
-        log(f"staggered autotune {prec}: sites/block {sb}, xcd swizzle {sw}")
+        sb, sw, sp = lat.stag_autotune(prec, 1)
+        log(f"staggered autotune {prec}: sites/block {sb}, xcd swizzle {sw}, split {sp}")
     g = qcdgen.rng(qcdgen.CONFIG_SEED_BASE + 6)
     shape = qcdgen.site_shape(L) + (3,)
     b = torch.from_numpy(g.standard_normal(shape) + 1j * g.standard_normal(shape)).cuda()
@@ -670,8 +670,8 @@ def bench_staggered(args):
     best = min(res, key=lambda k: res[k]["time_to_solution_ms"])
     # Goldstone pion: the 3 colour point-source propagators (one 3-field solve)
     # and the correlator, with the faster inner precision.
-    sb, sw = lat.stag_autotune(best, 3)
-    log(f"staggered autotune {best}, 3 fields: sites/block {sb}, xcd swizzle {sw}")
+    sb, sw, sp = lat.stag_autotune(best, 3)
+    log(f"staggered autotune {best}, 3 fields: sites/block {sb}, xcd swizzle {sw}, split {sp}")
     p = W.default_params(inner=best, delta=1e-2 if best != "f64" else 0.0)
     for _ in range(max(1, args.warmup)):
         G, st = lat.stag_propagator(mass, params=p)

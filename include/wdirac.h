@@ -266,13 +266,26 @@ wd_status wd_stag_apply(wd_lattice lat, void* y, const void* x, int32_t nrhs, do
                         int32_t prec, void* ws, size_t ws_bytes, void* stream);
 
 /* Autotune the staggered stencil's launch shape (sites per workgroup, XCD-
- * aware block order) for this lattice, precision and nrhs by timing every
- * candidate on stream (outputs must be bit-identical); the choice is kept in
- * a process-wide table used by later staggered launches (not part of the
- * exported text table).  Needs wd_stag_apply_workspace_bytes.  Blocks the
- * host.  The best_* outputs receive the choice (may be NULL). */
+ * aware block order, 1, 2 or 4 threads sharing the 8 hops of a site) for
+ * this lattice, precision and nrhs by timing every candidate of 128 to 256
+ * threads on stream (outputs with the same split must be bit-identical).
+ * The choice follows the rule of wd_autotune and is kept in a process-wide
+ * table used by later staggered
+ * launches (not part of the exported text table).  Needs
+ * wd_stag_apply_workspace_bytes.  Blocks the host.  The best_* outputs
+ * receive the choice (may be NULL). */
 wd_status wd_stag_autotune(wd_lattice lat, int32_t prec, int32_t nrhs, void* ws, size_t ws_bytes,
-                           int32_t* best_sites_per_block, int32_t* best_swizzle, void* stream);
+                           int32_t* best_sites_per_block, int32_t* best_swizzle, int32_t* best_split,
+                           void* stream);
+
+/* Set the staggered stencil's launch shape for this lattice, precision (of
+ * its registered store) and nrhs, as wd_stag_autotune would: sites per
+ * workgroup (a power of two), XCD-aware block order (0 / 1) and the number of
+ * threads (1, 2, 4) sharing a site's 8 hops, with split * sites_per_block *
+ * nrhs <= 256.  WD_EINVAL for any other shape, WD_ENOGAUGE without a store.
+ * Host only. */
+wd_status wd_stag_set_shape(wd_lattice lat, int32_t prec, int32_t nrhs, int32_t sites_per_block, int32_t swizzle,
+                            int32_t split);
 
 /* Workspace bytes for wd_stag_solve with these parameters and nrhs fields. */
 size_t wd_stag_solve_workspace_bytes(wd_lattice lat, const wd_solve_params* params, int32_t nrhs);
@@ -346,10 +359,11 @@ wd_status wd_time_read(const void* buf, size_t bytes, int32_t n, void* out, size
 
 /* Autotune the stencil launch shape (sites per workgroup, XCD-aware block
  * order, number of threads the 8 hops of a site are split over) for this
- * lattice, precision and nrhs by timing every candidate on stream.  Of the
- * candidates within 3 % of the fastest, the one with the fewest workgroups is
- * chosen (each reducing launch of the CG leaves one partial sum per workgroup
- * for stage 2 to gather).  The choice
+ * lattice, precision and nrhs by timing every candidate on stream.  Among
+ * the candidates whose workgroup count lets the CG fold its reductions (if
+ * any do), of those within 3 % of the fastest, the one with the fewest
+ * workgroups is chosen, XCD-aware order first (each reducing launch of the
+ * CG leaves one partial sum per workgroup for stage 2 to gather).  The choice
  * is kept in a process-wide table keyed by (dims, prec, recon, nrhs) and used
  * by every later launch.  Candidates with the same split must produce
  * bit-identical output (checked).  Needs wd_apply_workspace_bytes(lat, prec,

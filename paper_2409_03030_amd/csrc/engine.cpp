@@ -104,14 +104,7 @@ struct Engine::Phase {
 // A reduction is finished by every block of the launch that consumes it
 // (FIN_CG in the vector update, the staggered alpha in its residual update)
 // when each slot has at most kFoldPartials block partials and the consumer's
-// blocks together read at most kFoldReads of them: every block repeats the
-// whole gather, so the fold only pays off while partials and blocks are few.
-// (Measured at 16^3x32: 1024 stencil blocks each gathering 1024 partials
-// cost the staggered FP64 CG about 9 us per iteration, far more than a
-// finalize kernel; 512 vector-update blocks gathering 1024 partials were still
-// 6 us per iteration faster than the finalize kernel in the FP32 Wilson CG.)
-constexpr int kFoldPartials = 1024;
-constexpr long long kFoldReads = 1LL << 19;
+// blocks together read at most kFoldReads of them (wd_host.h).
 
 // Consumer blocks of a slot: the stencil's own block count, or the vector
 // kernels' (blas_sblk sites per block).

@@ -278,6 +278,62 @@ wd_status check_lattice_for(const wd_lattice_s* lat, int prec, int precond) {
   return WD_OK;
 }
 
+// Measured at 16^3x32, FP32: 256-thread blocks gave the same stencil time as
+// 128-thread blocks (10.3 against 10.4 us inside the solve) but a 3 % faster
+// solve (11.0 against 11.4 ms) with half the partials; the staggered FP32
+// stencil's fastest shape (1024 blocks of 4 threads per site) lost both folds
+// and made its solve 25 % slower.  Between equal block counts the XCD-aware
+// order wins: with it every kernel of the CG (whatever its block size) gives
+// each XCD the same contiguous eighth of the sites, so a vector written by
+// one kernel is read from the same L2 by the next (staggered FP32 solve 5.6
+// against 5.9 ms, FP16-inner Wilson solve 10.1 against 10.5 ms, with bare
+// stencil times within noise of each other).
+Tune pick_shape(const std::vector<std::pair<Tune, double>>& timed_all, long long n, int nrhs, Tune fallback) {
+  constexpr double kTuneSlack = 1.03;
+  // the XCD-aware order of a (sblk, split) pair is kept unless it is more than
+  // kSwzSlack slower than the plain order in the bare stencil, which times
+  // one kernel alone and so misses the cross-kernel L2 reuse
+  constexpr double kSwzSlack = 1.10;
+  std::vector<std::pair<Tune, double>> timed;
+  for (const auto& c : timed_all) {
+    const std::pair<Tune, double>* other = nullptr;
+    for (const auto& d : timed_all)
+      if (d.first.sblk == c.first.sblk && d.first.split == c.first.split && d.first.swz != c.first.swz) other = &d;
+    if (!other) {
+      timed.push_back(c);
+    } else if (c.first.swz == 1) {
+      if (c.second <= kSwzSlack * other->second) timed.push_back({c.first, std::min(c.second, other->second)});
+    } else if (other->second > kSwzSlack * c.second) {
+      timed.push_back(c);
+    }
+  }
+  auto blocks_of = [&](const Tune& t) { return (n + t.sblk - 1) / t.sblk; };
+  auto folds = [&](const Tune& t) {
+    const long long b = blocks_of(t), parts = b * nrhs;
+    return parts <= kFoldPartials && b * parts <= kFoldReads;
+  };
+  bool any_fold = false;
+  for (const auto& c : timed) any_fold = any_fold || folds(c.first);
+  double best = 1e30;
+  for (const auto& c : timed)
+    if (!any_fold || folds(c.first)) best = std::min(best, c.second);
+  Tune bt = fallback;
+  long long bt_blocks = -1;
+  double bt_ms = 1e30;
+  for (const auto& c : timed) {
+    if ((any_fold && !folds(c.first)) || c.second > kTuneSlack * best) continue;
+    const long long b = blocks_of(c.first);
+    const bool better = bt_blocks < 0 || b < bt_blocks ||
+                        (b == bt_blocks && (c.first.swz > bt.swz || (c.first.swz == bt.swz && c.second < bt_ms)));
+    if (better) {
+      bt = c.first;
+      bt_blocks = b;
+      bt_ms = c.second;
+    }
+  }
+  return bt;
+}
+
 }  // namespace wd
 
 using namespace wd;
@@ -661,8 +717,14 @@ wd_status wd_autotune(wd_lattice lat, int32_t prec, int32_t nrhs, void* ws, size
         Tune t{sblk, swz, split};
         if (!valid_tune(t, nrhs, prec)) continue;
         WD_HIP(hipMemsetAsync(w + 2 * vb, 0, vb, st));
-        double ms = 0.0;
-        if ((s = time_hop_shape(lat, prec, nrhs, HOP_PLAIN, 20, t, w, &ms, st)) != WD_OK) return s;
+        // the best of 3 timings of 20 launches: the shapes of a small lattice
+        // differ by a few percent, about the run-to-run spread of one timing
+        double ms = 1e30;
+        for (int rep = 0; rep < 3; ++rep) {
+          double m1 = 0.0;
+          if ((s = time_hop_shape(lat, prec, nrhs, HOP_PLAIN, 20, t, w, &m1, st)) != WD_OK) return s;
+          ms = std::min(ms, m1);
+        }
         // within one split the per-site arithmetic does not depend on the tiling:
         // every shape must produce the same bytes
         got.resize(vb);
@@ -675,28 +737,7 @@ wd_status wd_autotune(wd_lattice lat, int32_t prec, int32_t nrhs, void* ws, size
       }
     }
   }
-  // Among the shapes within kTuneSlack of the fastest stencil, the one with the
-  // fewest blocks: every reducing launch of the CG leaves one partial per
-  // block, and each partial is gathered again by stage 2 (in every block of
-  // the vector update when it is folded there).  Measured at 16^3x32, FP32:
-  // 256-thread blocks gave the same stencil time as 128-thread blocks (10.3
-  // against 10.4 us inside the solve) but a 3 % faster solve (11.0 against
-  // 11.4 ms) with half the partials.
-  constexpr double kTuneSlack = 1.03;
-  double best = 1e30;
-  for (const auto& c : timed) best = std::min(best, c.second);
-  Tune bt{default_sblk(nrhs), 1, 1};
-  long long bt_blocks = -1;
-  double bt_ms = 1e30;
-  for (const auto& c : timed) {
-    if (c.second > kTuneSlack * best) continue;
-    const long long blocks = ((long long)lat->g.n + c.first.sblk - 1) / c.first.sblk;
-    if (bt_blocks < 0 || blocks < bt_blocks || (blocks == bt_blocks && c.second < bt_ms)) {
-      bt = c.first;
-      bt_blocks = blocks;
-      bt_ms = c.second;
-    }
-  }
+  const Tune bt = pick_shape(timed, lat->g.n, nrhs, Tune{default_sblk(nrhs), 1, 1});
   tune_store(lat, prec, lat->store[prec].recon, nrhs, bt);
   if (best_sites_per_block) *best_sites_per_block = bt.sblk;
   if (best_swizzle) *best_swizzle = bt.swz;

@@ -1,7 +1,8 @@
 // The staggered stencil with fused CG epilogues, its CG vector kernels and
 // the colour-vector layout conversions.  Same launch descriptors, masks and
-// deterministic two-stage reductions as the Wilson kernels; one thread per
-// (output site, rhs).  The CG runs on the even block
+// deterministic two-stage reductions as the Wilson kernels; one, two or four
+// threads per (output site, rhs), which split its 8 hops.  The CG runs on the
+// even block
 // M_e = m^2 - H_eo H_oe (Hermitian positive definite):
 //   t = H_oe p ; <p, M_e p> = m^2 |p|^2 + |t|^2        S_NORM  (alpha partials)
 //   alpha ; r -= alpha (m^2 p - H_eo t) ; |r|^2        S_CGR   (alpha folded in, FIN_CG)
@@ -12,7 +13,7 @@
 
 namespace wd {
 
-template <int P, int R, int MODE>
+template <int P, int R, int MODE, int D>
 __global__ void __launch_bounds__(kBlock) stag_kernel(const Launch L) {
   using T = typename RealOf<P>::T;
   const Tile t = make_tile(L);
@@ -32,11 +33,40 @@ __global__ void __launch_bounds__(kBlock) stag_kernel(const Launch L) {
   const size_t ne = (size_t)S.g.n * L.nrhs;
   const size_t e = (size_t)t.site * L.nrhs + t.rhs;
   const bool sel = t.valid && (fold_alpha ? s_active[t.rhs] != 0 : rhs_selected(S.st, L.mask, t.rhs));
-  double v = 0.0;
+  cvec<T> h;
   if (sel) {
     const char* in = (const char*)S.in + (both ? (size_t)(1 - par) * S.vstride : 0);
-    cvec<T> h;
-    stag_site<P, R>(S.g, par, t.site, t.rhs, L.nrhs, S.gauge, in, S.bc, h);  // 2 H in
+    stag_site<P, R, D>(S.g, par, t.site, t.rhs, L.nrhs, S.gauge, in, S.bc, t.part, h);  // (share of) 2 H in
+  }
+  if constexpr (D > 1) {
+    // parts 1..D-1 hand their sums to part 0, which adds them in part order
+    // and alone runs the epilogue
+    __shared__ T lds_h[(D - 1) * 6 * (kBlock / D)];
+    const int per = L.sblk * L.nrhs;
+    const int loc = (int)threadIdx.x - t.part * per;
+    if (sel && t.part > 0) {
+      T* q = lds_h + (size_t)(t.part - 1) * 6 * per + loc;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        q[(2 * k) * per] = h.c[k].re;
+        q[(2 * k + 1) * per] = h.c[k].im;
+      }
+    }
+    __syncthreads();
+    if (sel && t.part == 0) {
+#pragma unroll
+      for (int pp = 1; pp < D; ++pp) {
+        const T* q = lds_h + (size_t)(pp - 1) * 6 * per + loc;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+          h.c[k].re += q[(2 * k) * per];
+          h.c[k].im += q[(2 * k + 1) * per];
+        }
+      }
+    }
+  }
+  double v = 0.0;
+  if (sel && t.part == 0) {
     const size_t pv = both ? (size_t)par * S.vstride : 0;
     if (MODE == S_PLAIN || MODE == S_NORM) {
 #pragma unroll
@@ -97,32 +127,43 @@ __global__ void __launch_bounds__(kBlock) stag_kernel(const Launch L) {
   if (L.fin != FIN_NONE) block_reduce_store(L, S, t, v);
 }
 
-template <int P, int R, int MODE>
+template <int P, int R, int MODE, int D>
 static hipError_t stag_one(const Launch& L, hipStream_t stream) {
-  hipLaunchKernelGGL((stag_kernel<P, R, MODE>), dim3((unsigned)L.total_blocks), dim3((unsigned)(L.sblk * L.nrhs)), 0,
-                     stream, L);
+  hipLaunchKernelGGL((stag_kernel<P, R, MODE, D>), dim3((unsigned)L.total_blocks),
+                     dim3((unsigned)(D * L.sblk * L.nrhs)), 0, stream, L);
   return hipGetLastError();
+}
+
+template <int P, int R, int MODE>
+static hipError_t stag_split(const Launch& L, hipStream_t stream) {
+  switch (L.split) {
+    case 1: return stag_one<P, R, MODE, 1>(L, stream);
+    case 2: return stag_one<P, R, MODE, 2>(L, stream);
+    case 4: return stag_one<P, R, MODE, 4>(L, stream);
+  }
+  return hipErrorInvalidValue;
 }
 
 template <int P, int R>
 static hipError_t stag_mode(const Launch& L, int mode, hipStream_t stream) {
   switch (mode) {
-    case S_PLAIN: return stag_one<P, R, S_PLAIN>(L, stream);
-    case S_XPAY: return stag_one<P, R, S_XPAY>(L, stream);
-    case S_NORM: return stag_one<P, R, S_NORM>(L, stream);
-    case S_CGR: return stag_one<P, R, S_CGR>(L, stream);
+    case S_PLAIN: return stag_split<P, R, S_PLAIN>(L, stream);
+    case S_XPAY: return stag_split<P, R, S_XPAY>(L, stream);
+    case S_NORM: return stag_split<P, R, S_NORM>(L, stream);
+    case S_CGR: return stag_split<P, R, S_CGR>(L, stream);
     case S_RESID:
-      if constexpr (P == F64) return stag_one<P, R, S_RESID>(L, stream);
+      if constexpr (P == F64) return stag_split<P, R, S_RESID>(L, stream);
       return hipErrorInvalidValue;
   }
   return hipErrorInvalidValue;
 }
 
+// L.split threads per (site, rhs): 1, 2 or 4, each taking 8 / split hops.
 hipError_t launch_stag(const Launch& L0, int prec, int recon, int mode, hipStream_t stream) {
   if (L0.total_blocks <= 0) return hipSuccess;
-  Launch L = L0;
-  L.split = 1;  // one thread per (site, rhs)
-  if (L.sblk * L.nrhs > kBlock) return hipErrorInvalidValue;
+  const Launch& L = L0;
+  if (L.split != 1 && L.split != 2 && L.split != 4) return hipErrorInvalidValue;
+  if (L.split * L.sblk * L.nrhs > kBlock) return hipErrorInvalidValue;
   if (prec == F64) return recon == 12 ? stag_mode<F64, 12>(L, mode, stream) : stag_mode<F64, 18>(L, mode, stream);
   if (prec == F32) return recon == 12 ? stag_mode<F32, 12>(L, mode, stream) : stag_mode<F32, 18>(L, mode, stream);
   return hipErrorInvalidValue;

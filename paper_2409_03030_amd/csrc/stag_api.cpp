@@ -5,6 +5,7 @@
 // with s = +1 for D = m + H and s = -1 for D^dag = m - H.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <vector>
@@ -125,7 +126,8 @@ wd_status wd_stag_apply(wd_lattice lat, void* y, const void* x, int32_t nrhs, do
 }
 
 wd_status wd_stag_autotune(wd_lattice lat, int32_t prec, int32_t nrhs, void* ws, size_t ws_bytes,
-                           int32_t* best_sites_per_block, int32_t* best_swizzle, void* stream) {
+                           int32_t* best_sites_per_block, int32_t* best_swizzle, int32_t* best_split,
+                           void* stream) {
   if (!lat || !ws) return fail(WD_EINVAL, "null argument");
   if (prec != F64 && prec != F32) return fail(WD_EINVAL, "the staggered operator runs at FP64 or FP32");
   if (nrhs < 1 || nrhs > kBlock / 2) return fail(WD_EINVAL, "nrhs out of range");
@@ -142,60 +144,88 @@ wd_status wd_stag_autotune(wd_lattice lat, int32_t prec, int32_t nrhs, void* ws,
   WD_HIP(hipMemcpyAsync(vin, pat.data(), vb, hipMemcpyHostToDevice, st));
   WD_HIP(hipStreamSynchronize(st));
   const int recon = lat->store[prec].recon;
-  std::vector<unsigned char> ref, got;
-  double best = 1e30;
-  Tune bt = stag_tune_lookup(lat, prec, recon, nrhs);
+  std::vector<unsigned char> ref[5], got;
+  std::vector<std::pair<Tune, double>> timed;
   hipEvent_t e0, e1;
   WD_HIP(hipEventCreate(&e0));
   WD_HIP(hipEventCreate(&e1));
   wd_status res = WD_OK;
-  // blocks of at least 128 threads: below that the per-block fixed costs of
-  // the CG kernels (the folded reductions) outweigh what the bare stencil gains
-  for (int sblk = 1; sblk <= kBlock && res == WD_OK; sblk *= 2) {
-    if (sblk * nrhs < kBlock / 2 || sblk * nrhs > kBlock) continue;
-    for (int swz = 0; swz <= 1 && res == WD_OK; ++swz) {
-      Launch L = base_launch(nrhs, Tune{sblk, swz, 1}, 1);
-      L.nslots = 1;
-      L.mask = MASK_NONE;
-      L.fin = FIN_NONE;
-      Slot& S = L.s[0];
-      fill_slot_geometry(S, lat, sblk, 1);
-      S.gauge = (const char*)lat->store[prec].ptr;
-      S.in = vin;
-      S.out = vout;
-      S.vstride = vb;
-      finish_launch(L);
-      hipError_t e = hipSuccess;
-      for (int i = 0; i < 2 && e == hipSuccess; ++i) e = launch_stag(L, prec, recon, S_PLAIN, st);
-      if (e == hipSuccess) e = hipEventRecord(e0, st);
-      for (int i = 0; i < 20 && e == hipSuccess; ++i) e = launch_stag(L, prec, recon, S_PLAIN, st);
-      if (e == hipSuccess) e = hipEventRecord(e1, st);
-      if (e == hipSuccess) e = hipEventSynchronize(e1);
-      float ms = 0.f;
-      if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-      std::vector<unsigned char>& dst = ref.empty() ? ref : got;
-      dst.resize(vb);
-      if (e == hipSuccess) e = hipMemcpy(dst.data(), vout, vb, hipMemcpyDeviceToHost);
-      if (e != hipSuccess) {
-        res = hip_fail(e, "staggered autotune launch");
-        break;
-      }
-      if (&dst == &got && got != ref) {
-        res = fail(WD_EDEVICE, "staggered stencil output differs between launch shapes (sblk %d swz %d)", sblk, swz);
-        break;
-      }
-      if (ms < best) {
-        best = ms;
-        bt = Tune{sblk, swz, 1};
+  // blocks of 128 to 256 threads: below that the per-block fixed costs of the
+  // CG kernels (the folded reductions) outweigh what the bare stencil gains;
+  // split threads share the 8 hops of a site
+  for (int split = 1; split <= 4 && res == WD_OK; split *= 2) {
+    for (int sblk = 1; sblk <= kBlock && res == WD_OK; sblk *= 2) {
+      const int threads = split * sblk * nrhs;
+      if (threads < kBlock / 2 || threads > kBlock) continue;
+      for (int swz = 0; swz <= 1 && res == WD_OK; ++swz) {
+        const Tune tn{sblk, swz, split};
+        Launch L = base_launch(nrhs, tn, 1);
+        L.nslots = 1;
+        L.mask = MASK_NONE;
+        L.fin = FIN_NONE;
+        Slot& S = L.s[0];
+        fill_slot_geometry(S, lat, sblk, 1);
+        S.gauge = (const char*)lat->store[prec].ptr;
+        S.in = vin;
+        S.out = vout;
+        S.vstride = vb;
+        finish_launch(L);
+        hipError_t e = hipSuccess;
+        for (int i = 0; i < 2 && e == hipSuccess; ++i) e = launch_stag(L, prec, recon, S_PLAIN, st);
+        // the best of 3 timings of 20 launches (shapes differ by a few percent)
+        float ms = 1e30f;
+        for (int rep = 0; rep < 3 && e == hipSuccess; ++rep) {
+          e = hipEventRecord(e0, st);
+          for (int i = 0; i < 20 && e == hipSuccess; ++i) e = launch_stag(L, prec, recon, S_PLAIN, st);
+          if (e == hipSuccess) e = hipEventRecord(e1, st);
+          if (e == hipSuccess) e = hipEventSynchronize(e1);
+          float m1 = 0.f;
+          if (e == hipSuccess) e = hipEventElapsedTime(&m1, e0, e1);
+          ms = std::min(ms, m1);
+        }
+        // within one split the sums do not depend on the tiling: every shape
+        // must produce the same bytes
+        std::vector<unsigned char>& dst = ref[split].empty() ? ref[split] : got;
+        dst.resize(vb);
+        if (e == hipSuccess) e = hipMemcpy(dst.data(), vout, vb, hipMemcpyDeviceToHost);
+        if (e != hipSuccess) {
+          res = hip_fail(e, "staggered autotune launch");
+          break;
+        }
+        if (&dst == &got && got != ref[split]) {
+          res = fail(WD_EDEVICE, "staggered stencil output differs between launch shapes (sblk %d swz %d split %d)",
+                     sblk, swz, split);
+          break;
+        }
+        timed.push_back({tn, (double)ms});
       }
     }
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (res != WD_OK) return res;
+  const Tune bt = pick_shape(timed, lat->g.n, nrhs, stag_tune_lookup(lat, prec, recon, nrhs));
   stag_tune_store(lat, prec, recon, nrhs, bt);
   if (best_sites_per_block) *best_sites_per_block = bt.sblk;
   if (best_swizzle) *best_swizzle = bt.swz;
+  if (best_split) *best_split = bt.split;
+  return WD_OK;
+}
+
+wd_status wd_stag_set_shape(wd_lattice lat, int32_t prec, int32_t nrhs, int32_t sites_per_block, int32_t swizzle,
+                            int32_t split) {
+  if (!lat) return fail(WD_EINVAL, "null lattice");
+  if (prec != F64 && prec != F32) return fail(WD_EINVAL, "the staggered operator runs at FP64 or FP32");
+  if (nrhs < 1 || nrhs > kBlock / 2) return fail(WD_EINVAL, "nrhs out of range");
+  if (!lat->store[prec].ptr) return fail(WD_ENOGAUGE, "no gauge store of precision %d registered", prec);
+  if (split != 1 && split != 2 && split != 4) return fail(WD_EINVAL, "split = %d must be 1, 2 or 4", split);
+  if (swizzle != 0 && swizzle != 1) return fail(WD_EINVAL, "swizzle must be 0 or 1");
+  if (sites_per_block < 1 || (sites_per_block & (sites_per_block - 1)) != 0)
+    return fail(WD_EINVAL, "sites_per_block = %d must be a power of two", sites_per_block);
+  if ((long long)split * sites_per_block * nrhs > kBlock)
+    return fail(WD_EINVAL, "split * sites_per_block * nrhs = %lld exceeds %d threads",
+                (long long)split * sites_per_block * nrhs, kBlock);
+  stag_tune_store(lat, prec, lat->store[prec].recon, nrhs, Tune{sites_per_block, swizzle, split});
   return WD_OK;
 }
 

@@ -53,6 +53,25 @@ struct Tune {
   int split;  // threads per (site, rhs) in the stencil: 1, 2 or 4
 };
 bool valid_tune(const Tune& t, int nrhs, int prec);
+
+// Fold limits of the CG reductions: a reduction is finished by every block
+// of the launch that consumes it only when each slot has at most
+// kFoldPartials block partials and the consumer's blocks together read at
+// most kFoldReads of them; every block repeats the whole gather, so the fold
+// only pays off while partials and blocks are few.  (Measured at 16^3x32:
+// 1024 stencil blocks each gathering 1024 partials cost the staggered FP64 CG
+// about 9 us per iteration, far more than a finalize kernel; 512
+// vector-update blocks gathering 1024 partials were still 6 us per iteration
+// faster than the finalize kernel in the FP32 Wilson CG.)
+constexpr int kFoldPartials = 1024;
+constexpr long long kFoldReads = 1LL << 19;
+
+// The autotuners' choice among timed stencil shapes for a lattice of n sites
+// per parity: the shapes whose block count lets the CG fold its reductions
+// (if any do), then of those within 3 % of the fastest the one with the
+// fewest blocks, preferring the XCD-aware block order.  Every reducing launch leaves one partial per block, and a
+// reduction that cannot be folded costs a finalize kernel (about 5 us).
+Tune pick_shape(const std::vector<std::pair<Tune, double>>& timed, long long n, int nrhs, Tune fallback);
 Tune tune_lookup(const wd_lattice_s* lat, int prec, int recon, int nrhs);
 void tune_store(const wd_lattice_s* lat, int prec, int recon, int nrhs, Tune t);
 Tune stag_tune_lookup(const wd_lattice_s* lat, int prec, int recon, int nrhs);

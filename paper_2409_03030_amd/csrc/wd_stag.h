@@ -116,20 +116,39 @@ WD_HD void stag_dir(const Geom& g, const Coord& k, int parity, int s, int rhs, i
   stag_accumulate<T, DIR>(u, v, sign < 0, acc);
 }
 
-// 2 (H in)(x) at output site (parity, s) for one rhs.
-template <int P, int R>
+// Hops H0 .. H0 + NH - 1 of 2 (H in)(x), accumulated in hop order (hop h is
+// direction h / 2, forward for even h and backward for odd h).
+template <int P, int R, int H0, int NH>
+WD_HD void stag_hops(const Geom& g, const Coord& k, int parity, int s, int rhs, int nrhs, const char* gauge,
+                     const void* in, const float bc[4], cvec<typename RealOf<P>::T>& acc) {
+  if constexpr (NH > 0) {
+    constexpr int MU = H0 >> 1;
+    constexpr int DIR = (H0 & 1) ? -1 : 1;
+    stag_dir<P, R, MU, DIR>(g, k, parity, s, rhs, nrhs, gauge, in, bc[MU], acc);
+    stag_hops<P, R, H0 + 1, NH - 1>(g, k, parity, s, rhs, nrhs, gauge, in, bc, acc);
+  }
+}
+
+// Share `part` of the D shares (8 / D consecutive hops each) of 2 (H in)(x)
+// at output site (parity, s) for one rhs; D = 1 is the whole sum.
+template <int P, int R, int D>
 WD_HD void stag_site(const Geom& g, int parity, int s, int rhs, int nrhs, const char* gauge, const void* in,
-                     const float bc[4], cvec<typename RealOf<P>::T>& acc) {
+                     const float bc[4], int part, cvec<typename RealOf<P>::T>& acc) {
   const Coord k = site_coord(g, parity, s);
   cvec_zero(acc);
-  stag_dir<P, R, 0, +1>(g, k, parity, s, rhs, nrhs, gauge, in, bc[0], acc);
-  stag_dir<P, R, 0, -1>(g, k, parity, s, rhs, nrhs, gauge, in, bc[0], acc);
-  stag_dir<P, R, 1, +1>(g, k, parity, s, rhs, nrhs, gauge, in, bc[1], acc);
-  stag_dir<P, R, 1, -1>(g, k, parity, s, rhs, nrhs, gauge, in, bc[1], acc);
-  stag_dir<P, R, 2, +1>(g, k, parity, s, rhs, nrhs, gauge, in, bc[2], acc);
-  stag_dir<P, R, 2, -1>(g, k, parity, s, rhs, nrhs, gauge, in, bc[2], acc);
-  stag_dir<P, R, 3, +1>(g, k, parity, s, rhs, nrhs, gauge, in, bc[3], acc);
-  stag_dir<P, R, 3, -1>(g, k, parity, s, rhs, nrhs, gauge, in, bc[3], acc);
+  if constexpr (D == 1) {
+    stag_hops<P, R, 0, 8>(g, k, parity, s, rhs, nrhs, gauge, in, bc, acc);
+  } else if constexpr (D == 2) {
+    if (part == 0) stag_hops<P, R, 0, 4>(g, k, parity, s, rhs, nrhs, gauge, in, bc, acc);
+    else stag_hops<P, R, 4, 4>(g, k, parity, s, rhs, nrhs, gauge, in, bc, acc);
+  } else {
+    switch (part) {
+      case 0: stag_hops<P, R, 0, 2>(g, k, parity, s, rhs, nrhs, gauge, in, bc, acc); break;
+      case 1: stag_hops<P, R, 2, 2>(g, k, parity, s, rhs, nrhs, gauge, in, bc, acc); break;
+      case 2: stag_hops<P, R, 4, 2>(g, k, parity, s, rhs, nrhs, gauge, in, bc, acc); break;
+      default: stag_hops<P, R, 6, 2>(g, k, parity, s, rhs, nrhs, gauge, in, bc, acc); break;
+    }
+  }
 }
 
 }  // namespace wd

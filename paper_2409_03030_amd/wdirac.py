@@ -114,8 +114,9 @@ _SIGS = [
     ("wd_ta_add", C.c_int32, [_P, _P, C.c_double, _P, _P]),
     ("wd_stag_apply_workspace_bytes", C.c_size_t, [_P, C.c_int32, C.c_int32]),
     ("wd_stag_apply", C.c_int32, [_P, _P, _P, C.c_int32, C.c_double, C.c_int32, C.c_int32, _P, C.c_size_t, _P]),
+    ("wd_stag_set_shape", C.c_int32, [_P, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32]),
     ("wd_stag_autotune", C.c_int32, [_P, C.c_int32, C.c_int32, _P, C.c_size_t, C.POINTER(C.c_int32),
-                                     C.POINTER(C.c_int32), _P]),
+                                     C.POINTER(C.c_int32), C.POINTER(C.c_int32), _P]),
     ("wd_stag_solve_workspace_bytes", C.c_size_t, [_P, C.POINTER(SolveParams), C.c_int32]),
     ("wd_stag_solve", C.c_int32, [_P, _P, _P, C.c_int32, C.POINTER(C.c_double), C.c_int32, C.POINTER(SolveParams),
                                   _P, C.c_size_t, C.POINTER(SolveStats), _P]),
@@ -439,14 +440,19 @@ class Lattice:
         return y
 
     def stag_autotune(self, prec="f64", nrhs=1, stream=None):
-        """Tune the staggered stencil's launch shape; returns (sites per block, swizzle)."""
+        """Tune the staggered stencil's launch shape; returns (sites per block, swizzle, split)."""
         nb = int(lib().wd_stag_apply_workspace_bytes(self.handle, PREC[prec], nrhs))
         dev = next(iter(self.stores.values())).device
         ws = self._workspace(nb, dev, ("stag_apply", PREC[prec], nrhs))
-        sb, sw = C.c_int32(), C.c_int32()
+        sb, sw, sp = C.c_int32(), C.c_int32(), C.c_int32()
         _check(lib().wd_stag_autotune(self.handle, PREC[prec], nrhs, _ptr(ws), ws.numel(), C.byref(sb), C.byref(sw),
-                                      _stream(stream)), "wd_stag_autotune")
-        return sb.value, sw.value
+                                      C.byref(sp), _stream(stream)), "wd_stag_autotune")
+        return sb.value, sw.value, sp.value
+
+    def stag_set_shape(self, prec, nrhs, sites_per_block, swizzle, split):
+        """Force the staggered stencil's launch shape for (prec, nrhs)."""
+        _check(lib().wd_stag_set_shape(self.handle, PREC[prec], int(nrhs), int(sites_per_block), int(swizzle),
+                                       int(split)), "wd_stag_set_shape")
 
     def stag_solve(self, b, mass, params=None, dagger=False, out=None, stream=None, check=True):
         """x with D x = b (or D^dag x = b) for the staggered operator, even-odd CG.

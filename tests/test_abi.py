@@ -134,6 +134,8 @@ def test_staggered_argument_checks():
     assert lib.wd_stag_solve(h, dummy, dummy, 1, m, 0, C.byref(p16), dummy, big, stats, None) == W.WD_EINVAL
     assert lib.wd_stag_solve(h, dummy, dummy, 1, zero, 0, C.byref(p), dummy, big, stats, None) in (W.WD_EINVAL,
                                                                                                   W.WD_ENOGAUGE)
+    assert lib.wd_stag_set_shape(h, W.F64, 1, 128, 0, 1) == W.WD_ENOGAUGE
+    assert lib.wd_stag_set_shape(h, W.F16, 1, 128, 0, 1) == W.WD_EINVAL
     nw = lib.wd_pion_workspace_bytes(h)
     corr = (C.c_double * 4)()
     assert lib.wd_stag_pion_correlator(h, corr, dummy, 3, 4, dummy, nw, None) == W.WD_EINVAL   # t0 = Lt

@@ -140,8 +140,8 @@ def test_autotune_then_solve():
     b = _field(L, g)
     y0 = _host(lat.stag_apply(_dev(b), 0.2))
     for prec in ("f64", "f32"):
-        sb, sw = lat.stag_autotune(prec, 1)
-        assert sb * 1 >= 64 and sw in (0, 1)
+        sb, sw, sp = lat.stag_autotune(prec, 1)
+        assert 128 <= sb * sp <= 256 and sw in (0, 1) and sp in (1, 2, 4)
     y1 = _host(lat.stag_apply(_dev(b), 0.2))
     assert np.array_equal(y0, y1) or np.linalg.norm(y1 - y0) <= 1e-14 * np.linalg.norm(y0)
     x, st = lat.stag_solve(_dev(b), 0.2, params=W.default_params(inner="f32", delta=1e-2))
@@ -212,3 +212,37 @@ def test_full_size_propagator_and_pion():
         assert res <= 5e-9, (a, res)
     C = lat.stag_pion_correlator(G, origin[3])
     np.testing.assert_allclose(C, S.staggered_pion_correlator(Gh, origin[3]), rtol=1e-12, atol=0)
+
+
+@pytest.mark.parametrize("split,sblk,swz", [(1, 128, 0), (2, 64, 1), (2, 128, 0), (4, 32, 1), (4, 64, 0)])
+def test_launch_shapes_match_oracle(split, sblk, swz):
+    """Every staggered launch shape (hops split over 1, 2 or 4 threads, block
+    size, XCD order) gives the oracle's D and D^dag, with 1 and 2 fields, and
+    solves through the same shape (FP64 and FP32 inner) meet the oracle's
+    residual."""
+    W = _W()
+    L = (8, 6, 4, 10)   # dims used by no other staggered test: shapes are kept per lattice
+    g = qcdgen.rng(106)
+    U = qcdgen.links_exp(L, 0.4, g)
+    lat = _lattice(L, U)
+    m = 0.15
+    for nrhs in (1, 2):
+        sb = sblk if nrhs == 1 else sblk // 2
+        for prec in ("f64", "f32"):
+            lat.stag_set_shape(prec, nrhs, sb, swz, split)
+        x = _field(L, g, nrhs)
+        for prec, tol in (("f64", 1e-13), ("f32", 2e-6)):
+            for dagger in (False, True):
+                y = _host(lat.stag_apply(_dev(x), m, dagger=dagger, prec=prec))
+                op = S.apply_staggered_dag if dagger else S.apply_staggered
+                for r in range(nrhs):
+                    ref = op(U, x[r], m, BC)
+                    assert np.linalg.norm(y[r] - ref) / np.linalg.norm(ref) <= tol, (prec, dagger, r)
+        for inner in ("f64", "f32"):
+            p = W.default_params(inner=inner, delta=1e-2 if inner != "f64" else 0.0, tol=1e-12)
+            xs, st = lat.stag_solve(_dev(x), m, params=p)
+            xs = _host(xs)
+            for r in range(nrhs):
+                assert st[r]["status"] == 0, (inner, r)
+                res = np.linalg.norm(x[r] - S.apply_staggered(U, xs[r], m, BC)) / np.linalg.norm(x[r])
+                assert res <= 1e-10, (inner, r, res)
