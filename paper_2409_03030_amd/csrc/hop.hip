@@ -35,9 +35,12 @@ __global__ void __launch_bounds__(D == 8 ? kMaxBlock : kBlock) hop_kernel(const 
   }
   const Tile t = make_tile(L, lead);
   const Slot& S = L.s[t.slot];
-  // Launches with a reduction run every block: every block partial of the
-  // slot must be written for the finalize step.
-  if (L.fin == FIN_NONE && !slot_selected(L, S)) return;
+  // A slot with no selected rhs does nothing, not even its block partials:
+  // stage 2 changes no state of an unselected rhs whatever the sums (FIN_ALPHA
+  // leaves only running rhs active, FIN_CG acts on active rhs, FIN_RESID on
+  // held ones), and the mask of a reducing launch reads states that no block
+  // of it changes.  Masked iterations after convergence then cost a launch.
+  if (!slot_selected(L, S)) return;
   const bool both = L.parity == 2;
   const int par = t.parity;
   const size_t ne = (size_t)S.g.n * L.nrhs;
