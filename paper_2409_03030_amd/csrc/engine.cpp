@@ -341,6 +341,8 @@ static int round_block(int k, int kmax) {
   return std::min(best, kmax);
 }
 
+constexpr double kEstShrink = 0.8;
+
 int BlockPlanner::next(const RhsState* hs, size_t n, int inflight, const int* idx) {
   double best = 1e30;
   bool any = false;
@@ -360,15 +362,18 @@ int BlockPlanner::next(const RhsState* hs, size_t n, int inflight, const int* id
     double est = kmax;
     if (snap[q].iters >= 0 && s.iters > snap[q].iters && snap[q].rho > 0.0 && rho > 0.0) {
       const double rate = std::log(rho / snap[q].rho) / (s.iters - snap[q].iters);  // log decrease per iteration
-      if (rate < -1e-6) est = std::log(target / rho) / rate;
+      // CG converges faster than its recent rate towards the end (the residual
+      // falls super-linearly), so the extrapolation is shortened: an early
+      // block costs a poll, a late one masked iterations
+      if (rate < -1e-6) est = kEstShrink * std::log(target / rho) / rate;
     }
     snap[q] = Snap{s.iters, rho};
     est = std::max(0.0, est);
     best = std::min(best, est);
   }
   if (!any) return 0;
-  const double left = best - inflight;  // iterations still needed after the blocks in flight
-  if (left < 0.5) return -1;             // the event falls in a block in flight: wait for it
+  left = best - inflight;  // iterations still needed after the blocks in flight
+  if (left < 0.5) return -1;  // the event falls in a block in flight: wait for it
   return round_block((int)std::ceil(left), kmax);
 }
 
@@ -585,7 +590,7 @@ wd_status run_batch(std::vector<EItem>& items, const wd_solve_params& p, RhsStat
       }
       if ((result = post(K)) != WD_OK) break;
       iters_posted += K;
-      if (fly.size() < 2 && K >= plan.kmax) {
+      if (fly.size() < 2 && K >= plan.kmax && plan.left >= 2.0 * K) {
         // far from any event: keep a second block queued so the GPU never waits
         if ((result = post(K)) != WD_OK) break;
         iters_posted += K;
