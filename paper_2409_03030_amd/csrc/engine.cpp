@@ -343,12 +343,20 @@ static int round_block(int k, int kmax) {
 
 constexpr double kEstShrink = 0.8;
 
+// Iterations until each running rhs reaches its next event (convergence or a
+// reliable update), extrapolated from the decrease of its iterated residual:
+// the faster of the rate since the previous poll and the rate since the
+// first poll, shortened by kEstShrink (CG converges faster than its recent
+// rate towards the end, and after a reliable update the recent rate can be
+// near zero).  Where neither rate shows a decrease, a short probe block of
+// kmax / 4.  Over-estimates cost masked iterations (a launch each), under-
+// estimates an extra poll.
 int BlockPlanner::next(const RhsState* hs, size_t n, int inflight, const int* idx) {
   double best = 1e30;
   bool any = false;
   for (size_t j = 0; j < n; ++j) {
     const size_t q = idx ? (size_t)idx[j] : j;
-    if (snap.size() <= q) snap.resize(q + 1, Snap{-1, 0.0});
+    if (snap.size() <= q) snap.resize(q + 1, Snap{-1, 0.0, -1, 0.0});
     const RhsState& s = hs[q];
     if (s.state == ST_DONE || s.state == ST_NOTCONV || s.state == ST_NONFINITE) continue;
     any = true;
@@ -359,15 +367,20 @@ int BlockPlanner::next(const RhsState* hs, size_t n, int inflight, const int* id
     const double rho = s.iter_res2 > 0.0 ? s.iter_res2 : s.rho;
     double target = s.stop2;
     if (s.delta2 > 0.0) target = std::max(target, s.delta2 * s.max_rho);
-    double est = kmax;
-    if (snap[q].iters >= 0 && s.iters > snap[q].iters && snap[q].rho > 0.0 && rho > 0.0) {
-      const double rate = std::log(rho / snap[q].rho) / (s.iters - snap[q].iters);  // log decrease per iteration
-      // CG converges faster than its recent rate towards the end (the residual
-      // falls super-linearly), so the extrapolation is shortened: an early
-      // block costs a poll, a late one masked iterations
-      if (rate < -1e-6) est = kEstShrink * std::log(target / rho) / rate;
+    Snap& sn = snap[q];
+    double est = sn.iters0 < 0 ? (double)kmax : std::max(1.0, kmax / 4.0);
+    double rate = 0.0;  // log decrease per iteration (negative when decreasing)
+    if (sn.iters >= 0 && s.iters > sn.iters && sn.rho > 0.0 && rho > 0.0)
+      rate = std::min(rate, std::log(rho / sn.rho) / (s.iters - sn.iters));
+    if (sn.iters0 >= 0 && s.iters > sn.iters0 && sn.rho0 > 0.0 && rho > 0.0)
+      rate = std::min(rate, std::log(rho / sn.rho0) / (s.iters - sn.iters0));
+    if (rate < -1e-6) est = kEstShrink * std::log(target / rho) / rate;
+    if (sn.iters0 < 0 && rho > 0.0) {
+      sn.iters0 = s.iters;
+      sn.rho0 = rho;
     }
-    snap[q] = Snap{s.iters, rho};
+    sn.iters = s.iters;
+    sn.rho = rho;
     est = std::max(0.0, est);
     best = std::min(best, est);
   }

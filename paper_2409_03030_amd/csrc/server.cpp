@@ -150,8 +150,8 @@ static void worker_main(wd_server_s* S) {
       eng.set_changed();
       for (int r = 0; r < it->nrhs; ++r) {  // a new occupant of the slot: forget the old history
         const size_t q = (size_t)it->state_index + r;
-        if (plan.snap.size() <= q) plan.snap.resize(q + 1, BlockPlanner::Snap{-1, 0.0});
-        plan.snap[q] = BlockPlanner::Snap{-1, 0.0};
+        if (plan.snap.size() <= q) plan.snap.resize(q + 1, BlockPlanner::Snap{-1, 0.0, -1, 0.0});
+        plan.snap[q] = BlockPlanner::Snap{-1, 0.0, -1, 0.0};
       }
     }
     if (err != WD_OK) break;

@@ -184,8 +184,10 @@ class Engine {
 // earliest rhs is expected to reach its next event (delta drop or tolerance).
 struct BlockPlanner {
   struct Snap {
-    int iters;
+    int iters;    // at the previous poll
     double rho;
+    int iters0;   // at the first poll
+    double rho0;
   };
   std::vector<Snap> snap;
   int kmax = 32;
