@@ -288,12 +288,15 @@ wd_status check_lattice_for(const wd_lattice_s* lat, int prec, int precond) {
 // one kernel is read from the same L2 by the next (staggered FP32 solve 5.6
 // against 5.9 ms, FP16-inner Wilson solve 10.1 against 10.5 ms, with bare
 // stencil times within noise of each other).
-Tune pick_shape(const std::vector<std::pair<Tune, double>>& timed_all, long long n, int nrhs, Tune fallback) {
+Tune pick_shape(const std::vector<std::pair<Tune, double>>& timed_all, long long n, int nrhs, int per_iter,
+                double vec_bytes, Tune fallback) {
   constexpr double kTuneSlack = 1.03;
-  // the XCD-aware order of a (sblk, split) pair is kept unless it is more than
-  // kSwzSlack slower than the plain order in the bare stencil, which times
-  // one kernel alone and so misses the cross-kernel L2 reuse
-  constexpr double kSwzSlack = 1.10;
+  // The XCD-aware order of a (sblk, split) pair is kept unless it is more than
+  // kSwzSlack slower than the plain order in the bare stencil, which times one
+  // kernel alone and so misses the cross-kernel L2 reuse; that reuse needs a
+  // vector to fit in half of the XCDs' L2s (8 x 4 MB), otherwise only a tie
+  // goes to the XCD-aware order.
+  const double swz_slack = vec_bytes <= 16.0e6 ? 1.10 : 1.0;
   std::vector<std::pair<Tune, double>> timed;
   for (const auto& c : timed_all) {
     const std::pair<Tune, double>* other = nullptr;
@@ -302,8 +305,8 @@ Tune pick_shape(const std::vector<std::pair<Tune, double>>& timed_all, long long
     if (!other) {
       timed.push_back(c);
     } else if (c.first.swz == 1) {
-      if (c.second <= kSwzSlack * other->second) timed.push_back({c.first, std::min(c.second, other->second)});
-    } else if (other->second > kSwzSlack * c.second) {
+      if (c.second <= swz_slack * other->second) timed.push_back({c.first, std::min(c.second, other->second)});
+    } else if (other->second > swz_slack * c.second) {
       timed.push_back(c);
     }
   }
@@ -312,23 +315,26 @@ Tune pick_shape(const std::vector<std::pair<Tune, double>>& timed_all, long long
     const long long b = blocks_of(t), parts = b * nrhs;
     return parts <= kFoldPartials && b * parts <= kFoldReads;
   };
-  bool any_fold = false;
-  for (const auto& c : timed) any_fold = any_fold || folds(c.first);
+  // cost of a CG iteration: its per_iter stencil launches, plus a finalize
+  // kernel (about 5 us) for each of the two reductions that cannot be folded
+  auto cost = [&](const std::pair<Tune, double>& c) {
+    return per_iter * c.second + (folds(c.first) ? 0.0 : 2 * 0.005);
+  };
   double best = 1e30;
-  for (const auto& c : timed)
-    if (!any_fold || folds(c.first)) best = std::min(best, c.second);
+  for (const auto& c : timed) best = std::min(best, cost(c));
   Tune bt = fallback;
   long long bt_blocks = -1;
-  double bt_ms = 1e30;
+  double bt_cost = 1e30;
   for (const auto& c : timed) {
-    if ((any_fold && !folds(c.first)) || c.second > kTuneSlack * best) continue;
+    const double cc = cost(c);
+    if (cc > kTuneSlack * best) continue;
     const long long b = blocks_of(c.first);
     const bool better = bt_blocks < 0 || b < bt_blocks ||
-                        (b == bt_blocks && (c.first.swz > bt.swz || (c.first.swz == bt.swz && c.second < bt_ms)));
+                        (b == bt_blocks && (c.first.swz > bt.swz || (c.first.swz == bt.swz && cc < bt_cost)));
     if (better) {
       bt = c.first;
       bt_blocks = b;
-      bt_ms = c.second;
+      bt_cost = cc;
     }
   }
   return bt;
@@ -737,7 +743,7 @@ wd_status wd_autotune(wd_lattice lat, int32_t prec, int32_t nrhs, void* ws, size
       }
     }
   }
-  const Tune bt = pick_shape(timed, lat->g.n, nrhs, Tune{default_sblk(nrhs), 1, 1});
+  const Tune bt = pick_shape(timed, lat->g.n, nrhs, 4, (double)vb, Tune{default_sblk(nrhs), 1, 1});
   tune_store(lat, prec, lat->store[prec].recon, nrhs, bt);
   if (best_sites_per_block) *best_sites_per_block = bt.sblk;
   if (best_swizzle) *best_swizzle = bt.swz;

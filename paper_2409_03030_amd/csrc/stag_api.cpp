@@ -181,7 +181,7 @@ wd_status wd_stag_autotune(wd_lattice lat, int32_t prec, int32_t nrhs, void* ws,
           if (e == hipSuccess) e = hipEventSynchronize(e1);
           float m1 = 0.f;
           if (e == hipSuccess) e = hipEventElapsedTime(&m1, e0, e1);
-          ms = std::min(ms, m1);
+          ms = std::min(ms, m1 / 20.0f);  // per launch
         }
         // within one split the sums do not depend on the tiling: every shape
         // must produce the same bytes
@@ -204,7 +204,7 @@ wd_status wd_stag_autotune(wd_lattice lat, int32_t prec, int32_t nrhs, void* ws,
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (res != WD_OK) return res;
-  const Tune bt = pick_shape(timed, lat->g.n, nrhs, stag_tune_lookup(lat, prec, recon, nrhs));
+  const Tune bt = pick_shape(timed, lat->g.n, nrhs, 2, (double)vb, stag_tune_lookup(lat, prec, recon, nrhs));
   stag_tune_store(lat, prec, recon, nrhs, bt);
   if (best_sites_per_block) *best_sites_per_block = bt.sblk;
   if (best_swizzle) *best_swizzle = bt.swz;

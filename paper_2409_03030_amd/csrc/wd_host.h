@@ -66,12 +66,16 @@ bool valid_tune(const Tune& t, int nrhs, int prec);
 constexpr int kFoldPartials = 1024;
 constexpr long long kFoldReads = 1LL << 19;
 
-// The autotuners' choice among timed stencil shapes for a lattice of n sites
-// per parity: the shapes whose block count lets the CG fold its reductions
-// (if any do), then of those within 3 % of the fastest the one with the
-// fewest blocks, preferring the XCD-aware block order.  Every reducing launch leaves one partial per block, and a
-// reduction that cannot be folded costs a finalize kernel (about 5 us).
-Tune pick_shape(const std::vector<std::pair<Tune, double>>& timed, long long n, int nrhs, Tune fallback);
+// The autotuners' choice among timed stencil shapes (ms per launch) for a
+// lattice of n sites per parity: each shape is costed as per_iter of its
+// launches plus a finalize kernel (about 5 us) for each of the two CG
+// reductions its block count cannot fold; of the shapes within 3 % of the
+// cheapest, the one with the fewest blocks (every reducing launch leaves one
+// partial per block), preferring the XCD-aware order, which is also kept
+// within 10 % of the plain order while a vector (vec_bytes) fits in half of
+// the L2s.
+Tune pick_shape(const std::vector<std::pair<Tune, double>>& timed, long long n, int nrhs, int per_iter,
+                double vec_bytes, Tune fallback);
 Tune tune_lookup(const wd_lattice_s* lat, int prec, int recon, int nrhs);
 void tune_store(const wd_lattice_s* lat, int prec, int recon, int nrhs, Tune t);
 Tune stag_tune_lookup(const wd_lattice_s* lat, int prec, int recon, int nrhs);
@@ -192,6 +196,7 @@ struct BlockPlanner {
   std::vector<Snap> snap;
   int kmax = 32;
   double left = 0.0;  // iterations expected after the blocks in flight (last call of next)
+  int nrun = 0;       // rhs not yet finished (last call of next)
   // > 0: size of the next block; -1: wait for the blocks in flight; 0: all done.
   // idx (optional) lists the state entries to consider; else entries 0..n-1.
   int next(const RhsState* hs, size_t n, int inflight, const int* idx = nullptr);
