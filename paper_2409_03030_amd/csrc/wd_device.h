@@ -51,9 +51,6 @@ __device__ __forceinline__ wd_h2 cadd(wd_h2 a, wd_h2 b) { return a + b; }
 __device__ __forceinline__ wd_h2 csub(wd_h2 a, wd_h2 b) { return a - b; }
 __device__ __forceinline__ wd_h2 cadd_i(wd_h2 a, wd_h2 b) { return a + (wd_h2){-b.y, b.x}; }  // a + i b
 __device__ __forceinline__ wd_h2 csub_i(wd_h2 a, wd_h2 b) { return a + (wd_h2){b.y, -b.x}; }  // a - i b
-__device__ __forceinline__ wd_h2 h2_conj(wd_h2 v) {
-  return __builtin_bit_cast(wd_h2, __builtin_bit_cast(uint32_t, v) ^ 0x80000000u);
-}
 __device__ __forceinline__ wd_h2 h2_swap(wd_h2 v) { return v.yx; }
 __device__ __forceinline__ wd_h2 h2_bits(uint32_t u) { return __builtin_bit_cast(wd_h2, u); }
 __device__ __forceinline__ float dot2h(wd_h2 a, wd_h2 b, float c) {
