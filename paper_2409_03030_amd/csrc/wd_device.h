@@ -51,29 +51,13 @@ __device__ __forceinline__ wd_h2 cadd(wd_h2 a, wd_h2 b) { return a + b; }
 __device__ __forceinline__ wd_h2 csub(wd_h2 a, wd_h2 b) { return a - b; }
 __device__ __forceinline__ wd_h2 cadd_i(wd_h2 a, wd_h2 b) { return a + (wd_h2){-b.y, b.x}; }  // a + i b
 __device__ __forceinline__ wd_h2 csub_i(wd_h2 a, wd_h2 b) { return a + (wd_h2){b.y, -b.x}; }  // a - i b
+__device__ __forceinline__ wd_h2 h2_conj(wd_h2 v) {
+  return __builtin_bit_cast(wd_h2, __builtin_bit_cast(uint32_t, v) ^ 0x80000000u);
+}
 __device__ __forceinline__ wd_h2 h2_swap(wd_h2 v) { return v.yx; }
 __device__ __forceinline__ wd_h2 h2_bits(uint32_t u) { return __builtin_bit_cast(wd_h2, u); }
 __device__ __forceinline__ float dot2h(wd_h2 a, wd_h2 b, float c) {
   return __builtin_amdgcn_fdot2(__builtin_bit_cast(wd_hp2, a), __builtin_bit_cast(wd_hp2, b), c, false);
-}
-// The same with zero for c, and both with the high half of a negated
-// (a.re * b.re - a.im * b.im + c): the VOP3 form takes the constant 0 and the
-// neg_hi modifier, so a chain needs no zeroed register and no conjugated copy
-// of the link.
-__device__ __forceinline__ float dot2h0(wd_h2 a, wd_h2 b) {
-  float d;
-  asm("v_dot2_f32_f16 %0, %1, %2, 0" : "=v"(d) : "v"(a), "v"(b));
-  return d;
-}
-__device__ __forceinline__ float dot2h_nh(wd_h2 a, wd_h2 b, float c) {
-  float d;
-  asm("v_dot2_f32_f16 %0, %1, %2, %3 neg_hi:[1,0,0]" : "=v"(d) : "v"(a), "v"(b), "v"(c));
-  return d;
-}
-__device__ __forceinline__ float dot2h_nh0(wd_h2 a, wd_h2 b) {
-  float d;
-  asm("v_dot2_f32_f16 %0, %1, %2, 0 neg_hi:[1,0,0]" : "=v"(d) : "v"(a), "v"(b));
-  return d;
 }
 
 // A full spinor: 4 spins x 3 colours; component k = 3*spin + colour.
@@ -655,6 +639,7 @@ template <int R, int H>
 __device__ __forceinline__ void hop_finish16(HopBuf16& b, bool g5in, spinor<float>& acc) {
   constexpr int MU = H >> 1;
   constexpr int DIR = (H & 1) ? -1 : 1;
+  wd_h2 uc[9];  // (U.re, -U.im)
   if constexpr (R == 12) {
     su3<float> f;
 #pragma unroll
@@ -663,6 +648,8 @@ __device__ __forceinline__ void hop_finish16(HopBuf16& b, bool g5in, spinor<floa
 #pragma unroll
     for (int q = 6; q < 9; ++q) b.u[q] = (wd_h2){(_Float16)f.e[q].re, (_Float16)f.e[q].im};
   }
+#pragma unroll
+  for (int q = 0; q < 9; ++q) uc[q] = h2_conj(b.u[q]);
   if (g5in) {
 #pragma unroll
     for (int q = 6; q < 12; ++q) b.s[q] = -b.s[q];
@@ -676,22 +663,15 @@ __device__ __forceinline__ void hop_finish16(HopBuf16& b, bool g5in, spinor<floa
   for (int sp = 0; sp < 2; ++sp) {
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-      float re, im;
-      if (DIR > 0) {  // U h: U_aj
-        re = dot2h_nh0(b.u[3 * a], h[3 * sp]);
-        im = dot2h0(b.u[3 * a], hs[3 * sp]);
+      float re = 0.f, im = 0.f;
 #pragma unroll
-        for (int j = 1; j < 3; ++j) {
-          re = dot2h_nh(b.u[3 * a + j], h[3 * sp + j], re);
+      for (int j = 0; j < 3; ++j) {
+        if (DIR > 0) {  // U h: U_aj
+          re = dot2h(uc[3 * a + j], h[3 * sp + j], re);
           im = dot2h(b.u[3 * a + j], hs[3 * sp + j], im);
-        }
-      } else {        // U^dag h: conj(U_ja)
-        re = dot2h0(b.u[a], h[3 * sp]);
-        im = dot2h_nh0(b.u[a], hs[3 * sp]);
-#pragma unroll
-        for (int j = 1; j < 3; ++j) {
+        } else {        // U^dag h: conj(U_ja)
           re = dot2h(b.u[3 * j + a], h[3 * sp + j], re);
-          im = dot2h_nh(b.u[3 * j + a], hs[3 * sp + j], im);
+          im = dot2h(uc[3 * j + a], hs[3 * sp + j], im);
         }
       }
       gh.c[3 * sp + a] = {re, im};
