@@ -849,7 +849,7 @@ def main():
         print(json.dumps(summarize_pmc(*args.summarize_pmc), indent=1))
         return
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU: this build has no multi-GPU path (asked for --gpus {args.gpus}).",
+        print(f"bench.py runs on one GPU: the library has no multi-GPU path (asked for --gpus {args.gpus}).",
               file=sys.stderr)
         sys.exit(2)
     if args.workload == "cfg2":
