@@ -639,8 +639,13 @@ def bench_staggered(args):
     lat = W.Lattice(L, BC)
     for prec in ("f64", "f32"):
         lat.set_gauge(Ud, prec, 12)
-        sb, sw, sp = lat.stag_autotune(prec, 1)
-        log(f"staggered autotune {prec}: sites/block {sb}, xcd swizzle {sw}, split {sp}")
+        if args.stag_shape:
+            sb, sw, sp = (int(v) for v in args.stag_shape.split(","))
+            lat.stag_set_shape(prec, 1, sb, sw, sp)
+            log(f"staggered shape {prec} (given): sites/block {sb}, xcd swizzle {sw}, split {sp}")
+        else:
+            sb, sw, sp = lat.stag_autotune(prec, 1)
+            log(f"staggered autotune {prec}: sites/block {sb}, xcd swizzle {sw}, split {sp}")
     g = qcdgen.rng(qcdgen.CONFIG_SEED_BASE + 6)
     shape = qcdgen.site_shape(L) + (3,)
     b = torch.from_numpy(g.standard_normal(shape) + 1j * g.standard_normal(shape)).cuda()
@@ -842,6 +847,8 @@ def main():
     ap.add_argument("--lattice", default="24,24,24,48", help="stencil: lattice extents x,y,z,t")
     ap.add_argument("--save-tune", default=None, help="write the tuning table to this file")
     ap.add_argument("--tune-file", default=None, help="load this tuning table instead of autotuning")
+    ap.add_argument("--stag-shape", default=None,
+                    help="staggered: sites/block,swizzle,split for one field instead of autotuning (e.g. 128,1,2)")
     ap.add_argument("--summarize-pmc", nargs=4, metavar=("FETCH_CSV", "WRITE_CSV", "KERNEL", "LATTICE"),
                     help="fold two rocprofv3 --pmc runs into profiles/traffic.json and exit")
     args = ap.parse_args()
