@@ -238,3 +238,34 @@ def test_time_hop_modes():
     with pytest.raises(W.WDError) as e:
         lat.time_hop("f64", 1, n=5, mode=3)
     assert e.value.status == W.WD_EINVAL
+
+
+def test_autotune_shapes_and_solve():
+    """The autotuner returns a valid launch shape for every precision and for
+    1 and 4 fields, records it in the exported tuning table, and the stencil
+    and a solve through the tuned shapes still meet the oracle."""
+    W = _W()
+    L = (10, 4, 8, 6)   # dims used by no other test: the tuning table is process-wide
+    g = qcdgen.rng(139)
+    U = qcdgen.links_exp(L, 0.4, g)
+    lat = _lattice(L, U, [("f64", 12), ("f32", 12), ("f16", 12)])
+    for prec, p in (("f64", 0), ("f32", 1), ("f16", 2)):
+        for nrhs in (1, 4):
+            sb, sw, sp = lat.autotune(prec, nrhs)
+            assert sb > 0 and sb & (sb - 1) == 0 and sw in (0, 1) and sp in (1, 2, 4, 8), (prec, nrhs)
+            assert sp * sb * nrhs <= (512 if sp == 8 else 256) and not (prec == "f64" and sp == 8)
+            rows = [r.split() for r in W.tune_export().splitlines()]
+            want = [str(v) for v in (*L, p, 12, nrhs, sb, sw, sp)]
+            assert want in rows, (prec, nrhs, want)
+    psi = qcdgen.gaussian_spinor(L, g, 4)
+    e = O.even_mask(L)
+    for prec in ("f64", "f32", "f16"):
+        y = _host(lat.apply_DdagD(_dev(psi), 0.1365, precond=1, prec=prec))
+        for r in range(4):
+            assert _rel(y[r], O.apply_Ahat(U, psi[r] * e, 0.1365, BC)) < 2 * TOL[prec], (prec, r)
+    for inner in ("f64", "f32", "f16"):
+        x, st = lat.solve(_dev(psi), 0.1365, W.default_params(inner=inner, delta=1e-2 if inner != "f64" else 0.0))
+        xh = _host(x)
+        for r in range(4):
+            assert st[r]["status"] == 0, (inner, r)
+            assert O.residual_DdagD(U, xh[r], psi[r], 0.1365, BC, True) <= 1e-10, (inner, r)
