@@ -122,12 +122,17 @@ static bool fold_ok(const Launch& L, bool consumer_is_blas) {
   return true;
 }
 
-// Sites per block of the vector kernels: at least 128 threads whatever the
-// stencil's shape, so that a folded stage 2 (every block reading all the
-// stencil's partials) is not repeated by many small blocks.  (Measured at
-// 16^3x32: FP32 stencil blocks of 64 sites made the vector update 4 % of
-// the solve slower; 256-thread blocks were 0.5 % slower than 128 at FP64.)
+// Sites per block of the vector kernels, whatever the stencil's shape, so that
+// a folded stage 2 (every block reading all the stencil's partials) is not
+// repeated by many small blocks: 256 threads for one right-hand side, else
+// the fewest sites (a power of two) that give a block more than 64 threads.
+// (Measured at 16^3x32: with 256 threads rather than 128 the single-field
+// staggered FP64 and FP32 solves ran 1.6 % and 2.5 % faster and the Wilson
+// solves the same; the 12-field batched Wilson solves at 192 threads rather
+// than 96 ran 0.5 % slower.  FP32 stencil blocks of 64 sites, once used for
+// the vector kernels too, made the solve 4 % slower.)
 static int blas_sblk(int nrhs) {
+  if (nrhs == 1) return kBlock;
   int s = 1;
   while (2 * s * nrhs <= kBlock / 2) s *= 2;
   return s;
