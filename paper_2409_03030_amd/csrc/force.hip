@@ -56,7 +56,7 @@ __device__ __forceinline__ void force_link(const char* __restrict__ X, const cha
         q[3 * r + c] = cadd(q[3 * r + c], cadd(cjmul(ha.c[c], hb.c[r]), cjmul(ha.c[3 + c], hb.c[3 + r])));
   }
   su3<double> u;
-  LinkFmt<F64, R>::load(gauge + (size_t)(parity * 4 + MU) * link_dir_bytes<F64, R>(n), n, (size_t)s, u);
+  LinkFmt<F64, R>::load_nt(gauge + (size_t)(parity * 4 + MU) * link_dir_bytes<F64, R>(n), n, (size_t)s, u);
   const double f = (k.c[MU] == g.L[MU] - 1 && bc_mu < 0.f) ? -two_kappa : two_kappa;
 #pragma unroll
   for (int r = 0; r < 3; ++r)

@@ -181,15 +181,28 @@ template <typename T> WD_HD void reconstruct_row2(su3<T>& u) {
   u.e[8] = cconj(csub(cmul(u.e[0], u.e[4]), cmul(u.e[1], u.e[3])));
 }
 
-// FP64 links are read with non-temporal loads: each link is used once per
-// stencil launch, and at FP64 the neighbour spinors that are reused need the
-// L2 space (measured: +7% on 24^3x48 and 32^3x64, neutral on 16^3x32; the
-// same hint slowed the FP32 stencil, which keeps ordinary loads).
+// FP64 links: `load` is an ordinary load; `load_nt` carries the non-temporal
+// hint.  Each link is used once per stencil launch, so when a launch's working
+// set exceeds the Infinity Cache the hint keeps the links from evicting the
+// neighbour spinors that are reused (measured: +7 % on the 24^3x48 and
+// 32^3x64 stencils).  When the working set fits, ordinary loads leave the
+// links resident in the Infinity Cache for the next launch (the 16^3x32 FP64
+// solve 7.6 % faster).  The hint slowed the FP32 stencil, which always uses
+// ordinary loads.
 template <int R> struct LinkFmt<F64, R> {
   static constexpr int ncplx = R == 18 ? 9 : 6;
   static constexpr int chunk_bytes = 16;
   static constexpr int chunks = ncplx;
   WD_HD static void load(const void* base, size_t n, size_t s, su3<double>& u) {
+    const double2* v = (const double2*)base;
+#pragma unroll
+    for (int k = 0; k < ncplx; ++k) {
+      const double2 d = v[k * n + s];
+      u.e[k] = {d.x, d.y};
+    }
+    if (R == 12) reconstruct_row2(u);
+  }
+  WD_HD static void load_nt(const void* base, size_t n, size_t s, su3<double>& u) {
     const double2* v = (const double2*)base;
 #pragma unroll
     for (int k = 0; k < ncplx; ++k) {
@@ -500,7 +513,7 @@ template <typename TO, typename TI> WD_HD void spinor_convert(spinor<TO>& o, con
 // stencil (19.8 against 19.0 us at 16^3x32) and 1 % slower for FP32; at
 // FP64 a group of 2 hops took the 2-way split to one wave per SIMD.
 // ---------------------------------------------------------------------------
-template <int P, int R, int MU, int DIR>
+template <int P, int R, int MU, int DIR, bool NT>
 WD_HD void hop_dir(const Geom& g, const Coord& k, int parity, int s, int rhs, int nrhs,
                    const char* gauge, const void* in, float bc_sign, bool g5in,
                    spinor<typename RealOf<P>::T>& acc) {
@@ -524,52 +537,10 @@ WD_HD void hop_dir(const Geom& g, const Coord& k, int parity, int s, int rhs, in
   const int lp = DIR > 0 ? parity : 1 - parity;
   const size_t ls = DIR > 0 ? (size_t)s : (size_t)nb;
   const char* lbase = gauge + (size_t)(lp * 4 + MU) * link_dir_bytes<P, R>(n);
-  LinkFmt<P, R>::load(lbase, n, ls, u);
+  if constexpr (NT) LinkFmt<P, R>::load_nt(lbase, n, ls, u);
+  else LinkFmt<P, R>::load(lbase, n, ls, u);
   if (DIR > 0) mul_link(u, h, gh);
   else mul_link_dag(u, h, gh);
-  accumulate<MU, DIR>(acc, gh);
-}
-
-template <int P> struct HopBuf {
-  spinor<typename RealOf<P>::T> p;  // neighbour spinor
-  su3<typename RealOf<P>::T> u;     // U_mu(x) (forward) or U_mu(x - mu) (backward)
-  bool flip;                        // the hop crosses a boundary with sign -1
-};
-
-
-template <int P, int R, int H>
-WD_HD void hop_fetch(const Geom& g, const Coord& k, int parity, int s, int rhs, int nrhs, const char* gauge,
-                     const void* in, const float bc[4], HopBuf<P>& b) {
-  constexpr int MU = H >> 1;
-  constexpr int DIR = (H & 1) ? -1 : 1;
-  const size_t n = (size_t)g.n;
-  const size_t ne = n * (size_t)nrhs;
-  const int nb = neighbour_cb(g, k, MU, DIR);
-  SpinorFmt<P>::load(in, ne, (size_t)nb * nrhs + rhs, b.p);
-  // forward: U_mu(x), rooted at the output site (parity `parity`);
-  // backward: U_mu(x - mu), rooted at the neighbour (other parity).
-  const int lp = DIR > 0 ? parity : 1 - parity;
-  const size_t ls = DIR > 0 ? (size_t)s : (size_t)nb;
-  const char* lbase = gauge + (size_t)(lp * 4 + MU) * link_dir_bytes<P, R>(n);
-  LinkFmt<P, R>::load(lbase, n, ls, b.u);
-  const bool crosses = DIR > 0 ? (k.c[MU] == g.L[MU] - 1) : (k.c[MU] == 0);
-  b.flip = crosses && bc[MU] < 0.f;
-}
-
-template <int P, int H>
-WD_HD void hop_finish(HopBuf<P>& b, bool g5in, spinor<typename RealOf<P>::T>& acc) {
-  using T = typename RealOf<P>::T;
-  constexpr int MU = H >> 1;
-  constexpr int DIR = (H & 1) ? -1 : 1;
-  if (g5in) gamma5_inplace(b.p);
-  half_spinor<T> h, gh;
-  project<MU, DIR>(b.p, h);
-  if (b.flip) {
-#pragma unroll
-    for (int j = 0; j < 6; ++j) h.c[j] = cneg(h.c[j]);
-  }
-  if (DIR > 0) mul_link(b.u, h, gh);
-  else mul_link_dag(b.u, h, gh);
   accumulate<MU, DIR>(acc, gh);
 }
 
@@ -693,33 +664,21 @@ __device__ __forceinline__ void hop_finish_group16(std::integer_sequence<int, J.
   (hop_finish16<R, H0 + J>(b[J], g5in, acc), ...);
 }
 
-template <int P, int R, int H0, int... J>
-WD_HD void hop_fetch_group(std::integer_sequence<int, J...>, const Geom& g, const Coord& k, int parity, int s,
-                           int rhs, int nrhs, const char* gauge, const void* in, const float bc[4], HopBuf<P>* b) {
-  (hop_fetch<P, R, H0 + J>(g, k, parity, s, rhs, nrhs, gauge, in, bc, b[J]), ...);
-}
-
-template <int P, int H0, int... J>
-WD_HD void hop_finish_group(std::integer_sequence<int, J...>, HopBuf<P>* b, bool g5in,
-                            spinor<typename RealOf<P>::T>& acc) {
-  (hop_finish<P, H0 + J>(b[J], g5in, acc), ...);
-}
-
 // Hops H0 .. H0 + NH - 1, accumulated in hop order (FP16 in groups of 4).
-template <int P, int R, int H0, int NH>
+template <int P, int R, int H0, int NH, bool NT>
 WD_HD void hop_range(const Geom& g, const Coord& k, int parity, int s, int rhs, int nrhs, const char* gauge,
                      const void* in, const float bc[4], bool g5in, spinor<typename RealOf<P>::T>& acc) {
   if constexpr (NH > 0 && P != F16) {
     constexpr int MU = H0 >> 1;
     constexpr int DIR = (H0 & 1) ? -1 : 1;
-    hop_dir<P, R, MU, DIR>(g, k, parity, s, rhs, nrhs, gauge, in, bc[MU], g5in, acc);
-    hop_range<P, R, H0 + 1, NH - 1>(g, k, parity, s, rhs, nrhs, gauge, in, bc, g5in, acc);
+    hop_dir<P, R, MU, DIR, NT>(g, k, parity, s, rhs, nrhs, gauge, in, bc[MU], g5in, acc);
+    hop_range<P, R, H0 + 1, NH - 1, NT>(g, k, parity, s, rhs, nrhs, gauge, in, bc, g5in, acc);
   } else if constexpr (NH > 0) {
     constexpr int M = NH < 4 ? NH : 4;
     HopBuf16 b[M];
     hop_fetch_group16<R, H0>(std::make_integer_sequence<int, M>{}, g, k, parity, s, rhs, nrhs, gauge, in, bc, b);
     hop_finish_group16<R, H0>(std::make_integer_sequence<int, M>{}, b, g5in, acc);
-    hop_range<P, R, H0 + M, NH - M>(g, k, parity, s, rhs, nrhs, gauge, in, bc, g5in, acc);
+    hop_range<P, R, H0 + M, NH - M, NT>(g, k, parity, s, rhs, nrhs, gauge, in, bc, g5in, acc);
   }
 }
 
@@ -727,43 +686,35 @@ WD_HD void hop_range(const Geom& g, const Coord& k, int parity, int s, int rhs, 
 // D = 1 all directions, D = 2 (x,y) / (z,t), D = 4 one direction each,
 // D = 8 one hop each.  Parts are whole waves, so the branch on `part` is
 // uniform.
-template <int P, int R, int D>
+template <int P, int R, int D, bool NT>
 WD_HD void hop_part(const Geom& g, int parity, int s, int rhs, int nrhs, const char* gauge, const void* in,
                     const float bc[4], bool g5in, int part, spinor<typename RealOf<P>::T>& acc) {
   Coord k = site_coord(g, parity, s);
   spinor_zero(acc);
   if constexpr (D == 1) {
-    hop_range<P, R, 0, 8>(g, k, parity, s, rhs, nrhs, gauge, in, bc, g5in, acc);
+    hop_range<P, R, 0, 8, NT>(g, k, parity, s, rhs, nrhs, gauge, in, bc, g5in, acc);
   } else if constexpr (D == 2) {
-    if (part == 0) hop_range<P, R, 0, 4>(g, k, parity, s, rhs, nrhs, gauge, in, bc, g5in, acc);
-    else hop_range<P, R, 4, 4>(g, k, parity, s, rhs, nrhs, gauge, in, bc, g5in, acc);
+    if (part == 0) hop_range<P, R, 0, 4, NT>(g, k, parity, s, rhs, nrhs, gauge, in, bc, g5in, acc);
+    else hop_range<P, R, 4, 4, NT>(g, k, parity, s, rhs, nrhs, gauge, in, bc, g5in, acc);
   } else if constexpr (D == 4) {
     switch (part) {
-      case 0: hop_range<P, R, 0, 2>(g, k, parity, s, rhs, nrhs, gauge, in, bc, g5in, acc); break;
-      case 1: hop_range<P, R, 2, 2>(g, k, parity, s, rhs, nrhs, gauge, in, bc, g5in, acc); break;
-      case 2: hop_range<P, R, 4, 2>(g, k, parity, s, rhs, nrhs, gauge, in, bc, g5in, acc); break;
-      default: hop_range<P, R, 6, 2>(g, k, parity, s, rhs, nrhs, gauge, in, bc, g5in, acc); break;
+      case 0: hop_range<P, R, 0, 2, NT>(g, k, parity, s, rhs, nrhs, gauge, in, bc, g5in, acc); break;
+      case 1: hop_range<P, R, 2, 2, NT>(g, k, parity, s, rhs, nrhs, gauge, in, bc, g5in, acc); break;
+      case 2: hop_range<P, R, 4, 2, NT>(g, k, parity, s, rhs, nrhs, gauge, in, bc, g5in, acc); break;
+      default: hop_range<P, R, 6, 2, NT>(g, k, parity, s, rhs, nrhs, gauge, in, bc, g5in, acc); break;
     }
   } else {
     switch (part) {
-      case 0: hop_range<P, R, 0, 1>(g, k, parity, s, rhs, nrhs, gauge, in, bc, g5in, acc); break;
-      case 1: hop_range<P, R, 1, 1>(g, k, parity, s, rhs, nrhs, gauge, in, bc, g5in, acc); break;
-      case 2: hop_range<P, R, 2, 1>(g, k, parity, s, rhs, nrhs, gauge, in, bc, g5in, acc); break;
-      case 3: hop_range<P, R, 3, 1>(g, k, parity, s, rhs, nrhs, gauge, in, bc, g5in, acc); break;
-      case 4: hop_range<P, R, 4, 1>(g, k, parity, s, rhs, nrhs, gauge, in, bc, g5in, acc); break;
-      case 5: hop_range<P, R, 5, 1>(g, k, parity, s, rhs, nrhs, gauge, in, bc, g5in, acc); break;
-      case 6: hop_range<P, R, 6, 1>(g, k, parity, s, rhs, nrhs, gauge, in, bc, g5in, acc); break;
-      default: hop_range<P, R, 7, 1>(g, k, parity, s, rhs, nrhs, gauge, in, bc, g5in, acc); break;
+      case 0: hop_range<P, R, 0, 1, NT>(g, k, parity, s, rhs, nrhs, gauge, in, bc, g5in, acc); break;
+      case 1: hop_range<P, R, 1, 1, NT>(g, k, parity, s, rhs, nrhs, gauge, in, bc, g5in, acc); break;
+      case 2: hop_range<P, R, 2, 1, NT>(g, k, parity, s, rhs, nrhs, gauge, in, bc, g5in, acc); break;
+      case 3: hop_range<P, R, 3, 1, NT>(g, k, parity, s, rhs, nrhs, gauge, in, bc, g5in, acc); break;
+      case 4: hop_range<P, R, 4, 1, NT>(g, k, parity, s, rhs, nrhs, gauge, in, bc, g5in, acc); break;
+      case 5: hop_range<P, R, 5, 1, NT>(g, k, parity, s, rhs, nrhs, gauge, in, bc, g5in, acc); break;
+      case 6: hop_range<P, R, 6, 1, NT>(g, k, parity, s, rhs, nrhs, gauge, in, bc, g5in, acc); break;
+      default: hop_range<P, R, 7, 1, NT>(g, k, parity, s, rhs, nrhs, gauge, in, bc, g5in, acc); break;
     }
   }
-}
-
-// The whole hopping term at one site (all 8 hops in one thread).
-template <int P, int R>
-WD_HD void hop_site(const Geom& g, int parity, int s, int rhs, int nrhs, const char* gauge,
-                    const void* in, const float bc[4], bool g5in,
-                    spinor<typename RealOf<P>::T>& acc) {
-  hop_part<P, R, 1>(g, parity, s, rhs, nrhs, gauge, in, bc, g5in, 0, acc);
 }
 
 }  // namespace wd

@@ -40,10 +40,6 @@ size_t vec_bytes(int prec, size_t n, int nrhs);
 size_t gauge_bytes(const Geom& g, int prec, int recon);
 inline int acc_prec(int prec) { return prec == F16 ? F32 : prec; }
 
-// Algorithmic bytes of one stencil launch over `sites` output sites with
-// nrhs fields: 8 links per site (shared by the rhs), the input spinor once,
-// and the epilogue vectors of the mode once each.
-double hop_launch_bytes(int prec, int recon, int mode, long long sites, int nrhs);
 // The same for the staggered stencil (StagMode).
 double stag_launch_bytes(int prec, int recon, int mode, long long sites, int nrhs);
 

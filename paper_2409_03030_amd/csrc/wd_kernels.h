@@ -18,6 +18,11 @@ enum StagMode : int { S_PLAIN = 0, S_XPAY = 1, S_NORM = 2, S_CGR = 3, S_RESID = 
 // Stencil with epilogue `mode` (HopMode) at precision prec and link recon.
 hipError_t launch_hop(const Launch& L, int prec, int recon, int mode, hipStream_t stream);
 
+// Algorithmic bytes of one stencil launch over `sites` output sites with
+// nrhs fields: 8 links per site (shared by the rhs), the input spinor once,
+// and the epilogue vectors of the mode once each.
+double hop_launch_bytes(int prec, int recon, int mode, long long sites, int nrhs);
+
 // CG vector kernel `mode` (BlasMode); prec is the precision of p (the
 // accumulation vectors x, r are F32 when prec is F16, else prec).
 hipError_t launch_blas(const Launch& L, int prec, int mode, hipStream_t stream);

@@ -109,7 +109,9 @@ WD_HD void stag_dir(const Geom& g, const Coord& k, int parity, int s, int rhs, i
   const int lp = DIR > 0 ? parity : 1 - parity;
   const size_t ls = DIR > 0 ? (size_t)s : (size_t)nb;
   su3<T> u;
-  LinkFmt<P, R>::load(gauge + (size_t)(lp * 4 + MU) * link_dir_bytes<P, R>(n), n, ls, u);
+  const char* lbase = gauge + (size_t)(lp * 4 + MU) * link_dir_bytes<P, R>(n);
+  if constexpr (P == F64) LinkFmt<P, R>::load_nt(lbase, n, ls, u);  // used once per launch
+  else LinkFmt<P, R>::load(lbase, n, ls, u);
   const bool crosses = DIR > 0 ? (k.c[MU] == g.L[MU] - 1) : (k.c[MU] == 0);
   int sign = stag_phase(k, MU) * (DIR > 0 ? 1 : -1);
   if (crosses && bc_sign < 0.f) sign = -sign;

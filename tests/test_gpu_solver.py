@@ -235,6 +235,27 @@ def test_config2_full_size_fp64_cg():
         assert _oracle_resid(U, xm, b, 0.1365, eo=True) <= TOL
 
 
+def test_streamed_link_kernels_solve():
+    """20^3x32 (128000 sites per parity), exp(0.4 i H) links, kappa 0.137,
+    even-odd, FP64 recon-12 links: every FP64 stencil launch moves more than
+    half the Infinity Cache (147 MB and up), so it takes the kernels that read
+    the links with non-temporal loads, which the smaller lattices of the other
+    tests never reach.  The plain FP64 CG and the FP16-inner CG, whose reliable
+    updates run the FP64 true-residual stencil, both reach the oracle's 1e-10."""
+    L = (20, 20, 20, 32)
+    g = qcdgen.rng(qcdgen.CONFIG_SEED_BASE + 2)
+    U = qcdgen.links_exp(L, 0.4, g)
+    b = qcdgen.gaussian_spinor(L, qcdgen.rng(qcdgen.CONFIG_SEED_BASE + 102))
+    W = _W()
+    lat = _lattice(L, U, [("f64", 12), ("f16", 12)])
+    for inner in ("f64", "f16"):
+        p = W.default_params(inner=inner, delta=1e-2 if inner != "f64" else 0.0)
+        x, st = lat.solve(_dev(b), 0.137, p)
+        x = _host(x)
+        assert st[0]["status"] == 0 and st[0]["true_resid"] <= TOL, inner
+        assert _oracle_resid(U, x, b, 0.137, eo=True) <= TOL, inner
+
+
 def test_batch_mixed_nrhs_and_many_items():
     """More items than slots per launch, and items with different nrhs in one batch."""
     W = _W()
