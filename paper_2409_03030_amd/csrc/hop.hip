@@ -181,12 +181,7 @@ static hipError_t launch_mode(const Launch& L, int mode, bool nt, hipStream_t st
   return hipErrorInvalidValue;
 }
 
-// FP64 links take the non-temporal hint when the launch's algorithmic bytes
-// exceed half the 256 MB Infinity Cache.  (Measured: with ordinary loads the
-// 16^3x32 FP64 solve, whose launches move 75-100 MB, ran 7.6 % faster, and the
-// 24^3x48 solve, 255 MB and more per launch, 8 % slower.)
-constexpr double kStreamLinkBytes = 128e6;
-
+// FP64 links take the non-temporal hint above kStreamLinkBytes per launch.
 static bool stream_links(const Launch& L, int prec, int recon, int mode) {
   if (prec != F64) return false;
   long long sites = 0;

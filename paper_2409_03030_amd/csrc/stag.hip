@@ -13,8 +13,11 @@
 
 namespace wd {
 
-template <int P, int R, int MODE, int D>
-__global__ void __launch_bounds__(kBlock) stag_kernel(const Launch L) {
+// NT: FP64 links read with the non-temporal hint (stag_kernel_nt), for
+// launches whose working set exceeds the Infinity Cache (as in the Wilson
+// stencil).
+template <int P, int R, int MODE, int D, bool NT>
+__device__ __forceinline__ void stag_body(const Launch& L) {
   using T = typename RealOf<P>::T;
   const Tile t = make_tile(L);
   const Slot& S = L.s[t.slot];
@@ -36,7 +39,7 @@ __global__ void __launch_bounds__(kBlock) stag_kernel(const Launch L) {
   cvec<T> h;
   if (sel) {
     const char* in = (const char*)S.in + (both ? (size_t)(1 - par) * S.vstride : 0);
-    stag_site<P, R, D>(S.g, par, t.site, t.rhs, L.nrhs, S.gauge, in, S.bc, t.part, h);  // (share of) 2 H in
+    stag_site<P, R, D, NT>(S.g, par, t.site, t.rhs, L.nrhs, S.gauge, in, S.bc, t.part, h);  // (share of) 2 H in
   }
   if constexpr (D > 1) {
     // parts 1..D-1 hand their sums to part 0, which adds them in part order
@@ -128,44 +131,66 @@ __global__ void __launch_bounds__(kBlock) stag_kernel(const Launch L) {
 }
 
 template <int P, int R, int MODE, int D>
-static hipError_t stag_one(const Launch& L, hipStream_t stream) {
-  hipLaunchKernelGGL((stag_kernel<P, R, MODE, D>), dim3((unsigned)L.total_blocks),
-                     dim3((unsigned)(D * L.sblk * L.nrhs)), 0, stream, L);
+__global__ void __launch_bounds__(kBlock) stag_kernel(const Launch L) {
+  stag_body<P, R, MODE, D, false>(L);
+}
+
+template <int P, int R, int MODE, int D>
+__global__ void __launch_bounds__(kBlock) stag_kernel_nt(const Launch L) {
+  stag_body<P, R, MODE, D, true>(L);
+}
+
+template <int P, int R, int MODE, int D>
+static hipError_t stag_one(const Launch& L, bool nt, hipStream_t stream) {
+  const dim3 grid((unsigned)L.total_blocks), block((unsigned)(D * L.sblk * L.nrhs));
+  if constexpr (P == F64) {
+    if (nt) {
+      hipLaunchKernelGGL((stag_kernel_nt<P, R, MODE, D>), grid, block, 0, stream, L);
+      return hipGetLastError();
+    }
+  }
+  hipLaunchKernelGGL((stag_kernel<P, R, MODE, D>), grid, block, 0, stream, L);
   return hipGetLastError();
 }
 
 template <int P, int R, int MODE>
-static hipError_t stag_split(const Launch& L, hipStream_t stream) {
+static hipError_t stag_split(const Launch& L, bool nt, hipStream_t stream) {
   switch (L.split) {
-    case 1: return stag_one<P, R, MODE, 1>(L, stream);
-    case 2: return stag_one<P, R, MODE, 2>(L, stream);
-    case 4: return stag_one<P, R, MODE, 4>(L, stream);
+    case 1: return stag_one<P, R, MODE, 1>(L, nt, stream);
+    case 2: return stag_one<P, R, MODE, 2>(L, nt, stream);
+    case 4: return stag_one<P, R, MODE, 4>(L, nt, stream);
   }
   return hipErrorInvalidValue;
 }
 
 template <int P, int R>
-static hipError_t stag_mode(const Launch& L, int mode, hipStream_t stream) {
+static hipError_t stag_mode(const Launch& L, int mode, bool nt, hipStream_t stream) {
   switch (mode) {
-    case S_PLAIN: return stag_split<P, R, S_PLAIN>(L, stream);
-    case S_XPAY: return stag_split<P, R, S_XPAY>(L, stream);
-    case S_NORM: return stag_split<P, R, S_NORM>(L, stream);
-    case S_CGR: return stag_split<P, R, S_CGR>(L, stream);
+    case S_PLAIN: return stag_split<P, R, S_PLAIN>(L, nt, stream);
+    case S_XPAY: return stag_split<P, R, S_XPAY>(L, nt, stream);
+    case S_NORM: return stag_split<P, R, S_NORM>(L, nt, stream);
+    case S_CGR: return stag_split<P, R, S_CGR>(L, nt, stream);
     case S_RESID:
-      if constexpr (P == F64) return stag_split<P, R, S_RESID>(L, stream);
+      if constexpr (P == F64) return stag_split<P, R, S_RESID>(L, nt, stream);
       return hipErrorInvalidValue;
   }
   return hipErrorInvalidValue;
 }
 
 // L.split threads per (site, rhs): 1, 2 or 4, each taking 8 / split hops.
+// FP64 links take the non-temporal hint above kStreamLinkBytes per launch.
 hipError_t launch_stag(const Launch& L0, int prec, int recon, int mode, hipStream_t stream) {
   if (L0.total_blocks <= 0) return hipSuccess;
   const Launch& L = L0;
   if (L.split != 1 && L.split != 2 && L.split != 4) return hipErrorInvalidValue;
   if (L.split * L.sblk * L.nrhs > kBlock) return hipErrorInvalidValue;
-  if (prec == F64) return recon == 12 ? stag_mode<F64, 12>(L, mode, stream) : stag_mode<F64, 18>(L, mode, stream);
-  if (prec == F32) return recon == 12 ? stag_mode<F32, 12>(L, mode, stream) : stag_mode<F32, 18>(L, mode, stream);
+  long long sites = 0;
+  for (int k = 0; k < L.nslots; ++k) sites += (long long)L.s[k].g.n * (L.parity == 2 ? 2 : 1) * L.nrhs;
+  const bool nt = prec == F64 && stag_launch_bytes(prec, recon, mode, sites, L.nrhs) > kStreamLinkBytes;
+  if (prec == F64)
+    return recon == 12 ? stag_mode<F64, 12>(L, mode, nt, stream) : stag_mode<F64, 18>(L, mode, nt, stream);
+  if (prec == F32)
+    return recon == 12 ? stag_mode<F32, 12>(L, mode, nt, stream) : stag_mode<F32, 18>(L, mode, nt, stream);
   return hipErrorInvalidValue;
 }
 

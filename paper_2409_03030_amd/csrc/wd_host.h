@@ -40,9 +40,6 @@ size_t vec_bytes(int prec, size_t n, int nrhs);
 size_t gauge_bytes(const Geom& g, int prec, int recon);
 inline int acc_prec(int prec) { return prec == F16 ? F32 : prec; }
 
-// The same for the staggered stencil (StagMode).
-double stag_launch_bytes(int prec, int recon, int mode, long long sites, int nrhs);
-
 struct Tune {
   int sblk;   // sites per block (power of two; see valid_tune)
   int swz;    // XCD-aware block order

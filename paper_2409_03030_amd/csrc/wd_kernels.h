@@ -22,6 +22,16 @@ hipError_t launch_hop(const Launch& L, int prec, int recon, int mode, hipStream_
 // nrhs fields: 8 links per site (shared by the rhs), the input spinor once,
 // and the epilogue vectors of the mode once each.
 double hop_launch_bytes(int prec, int recon, int mode, long long sites, int nrhs);
+// The same for the staggered stencil (StagMode).
+double stag_launch_bytes(int prec, int recon, int mode, long long sites, int nrhs);
+
+// FP64 links take the non-temporal hint when a stencil launch's algorithmic
+// bytes exceed half the 256 MB Infinity Cache; below that, ordinary loads
+// leave them resident in the Infinity Cache for the next launch.  (Measured:
+// with ordinary loads the 16^3x32 FP64 Wilson solve, whose launches move
+// 75-100 MB, ran 7.6 % faster, and the 24^3x48 solve, 255 MB and more per
+// launch, 8 % slower.)
+constexpr double kStreamLinkBytes = 128e6;
 
 // CG vector kernel `mode` (BlasMode); prec is the precision of p (the
 // accumulation vectors x, r are F32 when prec is F16, else prec).

@@ -97,7 +97,7 @@ WD_HD void stag_accumulate(const su3<T>& u, const cvec<T>& v, bool neg, cvec<T>&
 
 // acc += eta_mu(x) * (+- boundary sign) * (U chi(x+mu) or -U^dag chi(x-mu)),
 // without the factor 1/2.
-template <int P, int R, int MU, int DIR>
+template <int P, int R, int MU, int DIR, bool NT>
 WD_HD void stag_dir(const Geom& g, const Coord& k, int parity, int s, int rhs, int nrhs, const char* gauge,
                     const void* in, float bc_sign, cvec<typename RealOf<P>::T>& acc) {
   using T = typename RealOf<P>::T;
@@ -110,7 +110,7 @@ WD_HD void stag_dir(const Geom& g, const Coord& k, int parity, int s, int rhs, i
   const size_t ls = DIR > 0 ? (size_t)s : (size_t)nb;
   su3<T> u;
   const char* lbase = gauge + (size_t)(lp * 4 + MU) * link_dir_bytes<P, R>(n);
-  if constexpr (P == F64) LinkFmt<P, R>::load_nt(lbase, n, ls, u);  // used once per launch
+  if constexpr (NT) LinkFmt<P, R>::load_nt(lbase, n, ls, u);
   else LinkFmt<P, R>::load(lbase, n, ls, u);
   const bool crosses = DIR > 0 ? (k.c[MU] == g.L[MU] - 1) : (k.c[MU] == 0);
   int sign = stag_phase(k, MU) * (DIR > 0 ? 1 : -1);
@@ -120,35 +120,35 @@ WD_HD void stag_dir(const Geom& g, const Coord& k, int parity, int s, int rhs, i
 
 // Hops H0 .. H0 + NH - 1 of 2 (H in)(x), accumulated in hop order (hop h is
 // direction h / 2, forward for even h and backward for odd h).
-template <int P, int R, int H0, int NH>
+template <int P, int R, int H0, int NH, bool NT>
 WD_HD void stag_hops(const Geom& g, const Coord& k, int parity, int s, int rhs, int nrhs, const char* gauge,
                      const void* in, const float bc[4], cvec<typename RealOf<P>::T>& acc) {
   if constexpr (NH > 0) {
     constexpr int MU = H0 >> 1;
     constexpr int DIR = (H0 & 1) ? -1 : 1;
-    stag_dir<P, R, MU, DIR>(g, k, parity, s, rhs, nrhs, gauge, in, bc[MU], acc);
-    stag_hops<P, R, H0 + 1, NH - 1>(g, k, parity, s, rhs, nrhs, gauge, in, bc, acc);
+    stag_dir<P, R, MU, DIR, NT>(g, k, parity, s, rhs, nrhs, gauge, in, bc[MU], acc);
+    stag_hops<P, R, H0 + 1, NH - 1, NT>(g, k, parity, s, rhs, nrhs, gauge, in, bc, acc);
   }
 }
 
 // Share `part` of the D shares (8 / D consecutive hops each) of 2 (H in)(x)
 // at output site (parity, s) for one rhs; D = 1 is the whole sum.
-template <int P, int R, int D>
+template <int P, int R, int D, bool NT>
 WD_HD void stag_site(const Geom& g, int parity, int s, int rhs, int nrhs, const char* gauge, const void* in,
                      const float bc[4], int part, cvec<typename RealOf<P>::T>& acc) {
   const Coord k = site_coord(g, parity, s);
   cvec_zero(acc);
   if constexpr (D == 1) {
-    stag_hops<P, R, 0, 8>(g, k, parity, s, rhs, nrhs, gauge, in, bc, acc);
+    stag_hops<P, R, 0, 8, NT>(g, k, parity, s, rhs, nrhs, gauge, in, bc, acc);
   } else if constexpr (D == 2) {
-    if (part == 0) stag_hops<P, R, 0, 4>(g, k, parity, s, rhs, nrhs, gauge, in, bc, acc);
-    else stag_hops<P, R, 4, 4>(g, k, parity, s, rhs, nrhs, gauge, in, bc, acc);
+    if (part == 0) stag_hops<P, R, 0, 4, NT>(g, k, parity, s, rhs, nrhs, gauge, in, bc, acc);
+    else stag_hops<P, R, 4, 4, NT>(g, k, parity, s, rhs, nrhs, gauge, in, bc, acc);
   } else {
     switch (part) {
-      case 0: stag_hops<P, R, 0, 2>(g, k, parity, s, rhs, nrhs, gauge, in, bc, acc); break;
-      case 1: stag_hops<P, R, 2, 2>(g, k, parity, s, rhs, nrhs, gauge, in, bc, acc); break;
-      case 2: stag_hops<P, R, 4, 2>(g, k, parity, s, rhs, nrhs, gauge, in, bc, acc); break;
-      default: stag_hops<P, R, 6, 2>(g, k, parity, s, rhs, nrhs, gauge, in, bc, acc); break;
+      case 0: stag_hops<P, R, 0, 2, NT>(g, k, parity, s, rhs, nrhs, gauge, in, bc, acc); break;
+      case 1: stag_hops<P, R, 2, 2, NT>(g, k, parity, s, rhs, nrhs, gauge, in, bc, acc); break;
+      case 2: stag_hops<P, R, 4, 2, NT>(g, k, parity, s, rhs, nrhs, gauge, in, bc, acc); break;
+      default: stag_hops<P, R, 6, 2, NT>(g, k, parity, s, rhs, nrhs, gauge, in, bc, acc); break;
     }
   }
 }

@@ -129,6 +129,25 @@ def test_full_size_solve():
         assert res <= 5e-9, (inner, res)
 
 
+def test_streamed_link_kernels_solve():
+    """20^3x32 with recon-18 FP64 links, mass 0.1: every FP64 staggered stencil
+    launch moves more than 128 MB (160 MB and up), so it takes the kernels that
+    read the links with non-temporal loads, which the smaller lattices of the
+    other tests never reach.  Plain FP64 and FP32 inner (FP64 reliable
+    updates) both meet the oracle's FP64 residual of D x = b."""
+    W = _W()
+    L = (20, 20, 20, 32)
+    U = qcdgen.links_exp(L, 0.3, qcdgen.rng(qcdgen.CONFIG_SEED_BASE + 1))
+    lat = _lattice(L, U, recon=18)
+    b = _field(L, qcdgen.rng(104))
+    for inner in ("f64", "f32"):
+        p = W.default_params(inner=inner, delta=1e-2 if inner != "f64" else 0.0)
+        x, st = lat.stag_solve(_dev(b), 0.1, params=p)
+        assert st[0]["status"] == 0, inner
+        res = np.linalg.norm(b - S.apply_staggered(U, _host(x), 0.1, BC)) / np.linalg.norm(b)
+        assert res <= 5e-9, (inner, res)
+
+
 def test_autotune_then_solve():
     """The staggered autotuner's shapes give the same stencil output; a solve
     with the tuned shapes still meets the oracle's residual."""
