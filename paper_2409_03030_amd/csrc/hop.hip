@@ -19,8 +19,8 @@ namespace wd {
 
 template <int P> struct AccOf { static constexpr int value = P == F16 ? F32 : P; };
 
-// NT: FP64 links read with the non-temporal hint (hop_kernel_nt), for launches
-// whose working set exceeds the Infinity Cache.
+// NT: links read with the non-temporal hint (hop_kernel_nt, FP64 and FP32),
+// for launches whose links cannot stay in the Infinity Cache (stream_links).
 template <int P, int R, int MODE, int D, bool NT>
 __device__ __forceinline__ void hop_body(const Launch& L) {
   using T = typename RealOf<P>::T;
@@ -144,7 +144,7 @@ template <int P, int R, int MODE, int D>
 static hipError_t launch_one(const Launch& L, bool nt, hipStream_t stream) {
   const int lead = L.prefin != FIN_NONE ? L.nslots : 0;  // finalize-only workgroups
   dim3 grid((unsigned)(L.total_blocks + lead)), block((unsigned)(D * L.sblk * L.nrhs));
-  if constexpr (P == F64) {
+  if constexpr (P != F16) {
     if (nt) {
       hipLaunchKernelGGL((hop_kernel_nt<P, R, MODE, D>), grid, block, 0, stream, L);
       return hipGetLastError();
@@ -181,12 +181,15 @@ static hipError_t launch_mode(const Launch& L, int mode, bool nt, hipStream_t st
   return hipErrorInvalidValue;
 }
 
-// FP64 links take the non-temporal hint above kStreamLinkBytes per launch.
+// Links take the non-temporal hint when the launch's link fields exceed
+// kStreamLinkBytes, or when an FP64 launch moves more than kStreamLaunchBytes
+// (FP64 and FP32; the FP16 stencil always loads them ordinarily).
 static bool stream_links(const Launch& L, int prec, int recon, int mode) {
-  if (prec != F64) return false;
+  if (prec == F16) return false;
   long long sites = 0;
   for (int k = 0; k < L.nslots; ++k) sites += (long long)L.s[k].g.n * (L.parity == 2 ? 2 : 1) * L.nrhs;
-  return hop_launch_bytes(prec, recon, mode, sites, L.nrhs) > kStreamLinkBytes;
+  return link_field_bytes(L, prec, recon) > kStreamLinkBytes ||
+         (prec == F64 && hop_launch_bytes(prec, recon, mode, sites, L.nrhs) > kStreamLaunchBytes);
 }
 
 hipError_t launch_hop(const Launch& L, int prec, int recon, int mode, hipStream_t stream) {

@@ -13,9 +13,8 @@
 
 namespace wd {
 
-// NT: FP64 links read with the non-temporal hint (stag_kernel_nt), for
-// launches whose working set exceeds the Infinity Cache (as in the Wilson
-// stencil).
+// NT: links read with the non-temporal hint (stag_kernel_nt), for launches
+// whose links cannot stay in the Infinity Cache (as in the Wilson stencil).
 template <int P, int R, int MODE, int D, bool NT>
 __device__ __forceinline__ void stag_body(const Launch& L) {
   using T = typename RealOf<P>::T;
@@ -143,7 +142,7 @@ __global__ void __launch_bounds__(kBlock) stag_kernel_nt(const Launch L) {
 template <int P, int R, int MODE, int D>
 static hipError_t stag_one(const Launch& L, bool nt, hipStream_t stream) {
   const dim3 grid((unsigned)L.total_blocks), block((unsigned)(D * L.sblk * L.nrhs));
-  if constexpr (P == F64) {
+  {
     if (nt) {
       hipLaunchKernelGGL((stag_kernel_nt<P, R, MODE, D>), grid, block, 0, stream, L);
       return hipGetLastError();
@@ -178,7 +177,8 @@ static hipError_t stag_mode(const Launch& L, int mode, bool nt, hipStream_t stre
 }
 
 // L.split threads per (site, rhs): 1, 2 or 4, each taking 8 / split hops.
-// FP64 links take the non-temporal hint above kStreamLinkBytes per launch.
+// Links take the non-temporal hint when the launch's link fields exceed
+// kStreamLinkBytes, or when an FP64 launch moves more than kStreamLaunchBytes.
 hipError_t launch_stag(const Launch& L0, int prec, int recon, int mode, hipStream_t stream) {
   if (L0.total_blocks <= 0) return hipSuccess;
   const Launch& L = L0;
@@ -186,7 +186,8 @@ hipError_t launch_stag(const Launch& L0, int prec, int recon, int mode, hipStrea
   if (L.split * L.sblk * L.nrhs > kBlock) return hipErrorInvalidValue;
   long long sites = 0;
   for (int k = 0; k < L.nslots; ++k) sites += (long long)L.s[k].g.n * (L.parity == 2 ? 2 : 1) * L.nrhs;
-  const bool nt = prec == F64 && stag_launch_bytes(prec, recon, mode, sites, L.nrhs) > kStreamLinkBytes;
+  const bool nt = link_field_bytes(L, prec, recon) > kStreamLinkBytes ||
+                  (prec == F64 && stag_launch_bytes(prec, recon, mode, sites, L.nrhs) > kStreamLaunchBytes);
   if (prec == F64)
     return recon == 12 ? stag_mode<F64, 12>(L, mode, nt, stream) : stag_mode<F64, 18>(L, mode, nt, stream);
   if (prec == F32)

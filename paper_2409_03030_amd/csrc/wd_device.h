@@ -15,6 +15,8 @@
 
 // Native vector type for non-temporal loads (the builtin takes clang vectors).
 typedef double wd_nt_d2 __attribute__((ext_vector_type(2)));
+typedef float wd_nt_f2 __attribute__((ext_vector_type(2)));
+typedef float wd_nt_f4 __attribute__((ext_vector_type(4)));
 
 namespace wd {
 
@@ -181,14 +183,11 @@ template <typename T> WD_HD void reconstruct_row2(su3<T>& u) {
   u.e[8] = cconj(csub(cmul(u.e[0], u.e[4]), cmul(u.e[1], u.e[3])));
 }
 
-// FP64 links: `load` is an ordinary load; `load_nt` carries the non-temporal
-// hint.  Each link is used once per stencil launch, so when a launch's working
-// set exceeds the Infinity Cache the hint keeps the links from evicting the
-// neighbour spinors that are reused (measured: +7 % on the 24^3x48 and
-// 32^3x64 stencils).  When the working set fits, ordinary loads leave the
-// links resident in the Infinity Cache for the next launch (the 16^3x32 FP64
-// solve 7.6 % faster).  The hint slowed the FP32 stencil, which always uses
-// ordinary loads.
+// FP64 and FP32 links: `load` is an ordinary load; `load_nt` carries the
+// non-temporal hint.  Each link is used once per stencil launch; the launcher
+// picks the hinted loads when the links cannot stay in the Infinity Cache
+// until the next launch (stream_links), so that they do not evict the
+// neighbour spinors that are reused.
 template <int R> struct LinkFmt<F64, R> {
   static constexpr int ncplx = R == 18 ? 9 : 6;
   static constexpr int chunk_bytes = 16;
@@ -229,6 +228,14 @@ template <> struct LinkFmt<F32, 18> {
       u.e[k] = {d.x, d.y};
     }
   }
+  WD_HD static void load_nt(const void* base, size_t n, size_t s, su3<float>& u) {
+    const float2* v = (const float2*)base;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+      const wd_nt_f2 d = __builtin_nontemporal_load((const wd_nt_f2*)&v[k * n + s]);
+      u.e[k] = {d.x, d.y};
+    }
+  }
   WD_HD static void store(void* base, size_t n, size_t s, const su3<float>& u) {
     float2* v = (float2*)base;
 #pragma unroll
@@ -244,6 +251,16 @@ template <> struct LinkFmt<F32, 12> {
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
       float4 d = v[k * n + s];
+      u.e[2 * k] = {d.x, d.y};
+      u.e[2 * k + 1] = {d.z, d.w};
+    }
+    reconstruct_row2(u);
+  }
+  WD_HD static void load_nt(const void* base, size_t n, size_t s, su3<float>& u) {
+    const float4* v = (const float4*)base;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const wd_nt_f4 d = __builtin_nontemporal_load((const wd_nt_f4*)&v[k * n + s]);
       u.e[2 * k] = {d.x, d.y};
       u.e[2 * k + 1] = {d.z, d.w};
     }

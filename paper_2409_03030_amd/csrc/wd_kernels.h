@@ -25,13 +25,36 @@ double hop_launch_bytes(int prec, int recon, int mode, long long sites, int nrhs
 // The same for the staggered stencil (StagMode).
 double stag_launch_bytes(int prec, int recon, int mode, long long sites, int nrhs);
 
-// FP64 links take the non-temporal hint when a stencil launch's algorithmic
-// bytes exceed half the 256 MB Infinity Cache; below that, ordinary loads
-// leave them resident in the Infinity Cache for the next launch.  (Measured:
-// with ordinary loads the 16^3x32 FP64 Wilson solve, whose launches move
-// 75-100 MB, ran 7.6 % faster, and the 24^3x48 solve, 255 MB and more per
-// launch, 8 % slower.)
-constexpr double kStreamLinkBytes = 128e6;
+// Bytes of the link fields that a launch reads: each distinct gauge field
+// once (several slots may share one lattice), n sites per parity, 4 links per
+// site.
+inline double link_field_bytes(const Launch& L, int prec, int recon) {
+  const double link = (prec == F64 ? 16.0 : prec == F32 ? 8.0 : 4.0) * (recon == 12 ? 6 : 9);
+  double b = 0.0;
+  for (int k = 0; k < L.nslots; ++k) {
+    bool seen = false;
+    for (int j = 0; j < k; ++j) seen = seen || L.s[j].gauge == L.s[k].gauge;
+    if (!seen) b += (double)L.s[k].g.n * 8 * link;
+  }
+  return b;
+}
+
+// A stencil reads each link once.  Its links take the non-temporal hint when
+// they cannot stay in the 256 MB Infinity Cache until the next launch: when
+// the link field exceeds three quarters of it (kStreamLinkBytes), or, at FP64,
+// when the launch itself moves more than three times its size
+// (kStreamLaunchBytes), so that nothing it reads survives to the next launch
+// anyway.  Otherwise ordinary loads leave the links resident there.
+// (Measured, hinted against ordinary: FP64 links of 50-75 MB (16^3x32) 8 %
+// slower solves; FP32 links of 127 MB (24^3x48) a 26 % slower stencil; FP64
+// links of 127-191 MB (24^3x24) 11-15 % slower stencils; 12 FP64 fields at
+// 16^3x32 (launches up to 0.65 GB) 4 % slower propagators; FP64 links of
+// 255-382 MB (24^3x48) and FP32 links of 402 MB (32^3x64) 8-13 % and 10 %
+// faster stencils.  The launch-size condition keeps the FP64 launches of many
+// fields, such as the reliable updates of 36 fields at 16^3x32 at 1-1.8 GB,
+// on the hinted loads.)
+constexpr double kStreamLinkBytes = 192e6;
+constexpr double kStreamLaunchBytes = 768e6;
 
 // CG vector kernel `mode` (BlasMode); prec is the precision of p (the
 // accumulation vectors x, r are F32 when prec is F16, else prec).

@@ -236,18 +236,19 @@ def test_config2_full_size_fp64_cg():
 
 
 def test_streamed_link_kernels_solve():
-    """20^3x32 (128000 sites per parity), exp(0.4 i H) links, kappa 0.137,
-    even-odd, FP64 recon-12 links: every FP64 stencil launch moves more than
-    half the Infinity Cache (147 MB and up), so it takes the kernels that read
-    the links with non-temporal loads, which the smaller lattices of the other
-    tests never reach.  The plain FP64 CG and the FP16-inner CG, whose reliable
-    updates run the FP64 true-residual stencil, both reach the oracle's 1e-10."""
-    L = (20, 20, 20, 32)
+    """24^3x28 (193536 sites per parity), exp(0.4 i H) links, kappa 0.137,
+    even-odd, FP64 recon-18 links: the link field (223 MB) exceeds three
+    quarters of the Infinity Cache, so the FP64 stencils take the kernels that
+    read the links with non-temporal loads, which the smaller lattices of the
+    other tests never reach.  The plain FP64 CG and the FP16-inner CG, whose
+    reliable updates run the FP64 true-residual stencil, both reach the
+    oracle's 1e-10."""
+    L = (24, 24, 24, 28)
     g = qcdgen.rng(qcdgen.CONFIG_SEED_BASE + 2)
     U = qcdgen.links_exp(L, 0.4, g)
     b = qcdgen.gaussian_spinor(L, qcdgen.rng(qcdgen.CONFIG_SEED_BASE + 102))
     W = _W()
-    lat = _lattice(L, U, [("f64", 12), ("f16", 12)])
+    lat = _lattice(L, U, [("f64", 18), ("f16", 12)])
     for inner in ("f64", "f16"):
         p = W.default_params(inner=inner, delta=1e-2 if inner != "f64" else 0.0)
         x, st = lat.solve(_dev(b), 0.137, p)

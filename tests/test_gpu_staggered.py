@@ -130,13 +130,14 @@ def test_full_size_solve():
 
 
 def test_streamed_link_kernels_solve():
-    """20^3x32 with recon-18 FP64 links, mass 0.1: every FP64 staggered stencil
-    launch moves more than 128 MB (160 MB and up), so it takes the kernels that
-    read the links with non-temporal loads, which the smaller lattices of the
-    other tests never reach.  Plain FP64 and FP32 inner (FP64 reliable
-    updates) both meet the oracle's FP64 residual of D x = b."""
+    """24^3x28 with recon-18 FP64 links, mass 0.1: the link field (223 MB)
+    exceeds three quarters of the Infinity Cache, so the FP64 staggered
+    stencils take the kernels that read the links with non-temporal loads,
+    which the smaller lattices of the other tests never reach.  Plain FP64 and
+    FP32 inner (FP64 reliable updates) both meet the oracle's FP64 residual of
+    D x = b."""
     W = _W()
-    L = (20, 20, 20, 32)
+    L = (24, 24, 24, 28)
     U = qcdgen.links_exp(L, 0.3, qcdgen.rng(qcdgen.CONFIG_SEED_BASE + 1))
     lat = _lattice(L, U, recon=18)
     b = _field(L, qcdgen.rng(104))
