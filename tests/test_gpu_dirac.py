@@ -193,6 +193,34 @@ def test_full_size_sampled_sites(L, width, kappa):
     assert _rel(got32, ref) < 1e-5
 
 
+def test_streamed_fp32_links_sampled_sites():
+    """24^3x56 with FP32 recon-18 links: the link field (223 MB) exceeds three
+    quarters of the Infinity Cache, so the FP32 Wilson and staggered stencils
+    take the kernels that read the links with non-temporal loads (smaller
+    FP32 link fields never do).  Wilson D at 128 sampled sites against the
+    site-wise oracle, and the staggered D against the oracle's full apply, both
+    within the FP32 tolerance."""
+    from oracle import staggered as S
+    L = (24, 24, 24, 56)
+    g = qcdgen.rng(qcdgen.CONFIG_SEED_BASE + 3)
+    U = qcdgen.links_exp(L, 0.4, g)
+    psi = qcdgen.gaussian_spinor(L, g)
+    lat = _lattice(L, U, [("f32", 18)])
+    y32 = _host(lat.apply_D(_dev(psi), 0.137, prec="f32"))
+    gs = qcdgen.rng(11)
+    sites = [tuple(int(gs.integers(0, L[m])) for m in range(4)) for _ in range(124)]
+    sites += [(0, 0, 0, 0), (L[0] - 1, L[1] - 1, L[2] - 1, L[3] - 1), (0, L[1] - 1, 0, L[3] - 1),
+              (L[0] - 1, 0, L[2] - 1, 0)]
+    ref = O.apply_D_sites(U, psi, 0.137, BC, sites)
+    got = np.array([y32[s[3], s[2], s[1], s[0]] for s in sites])
+    assert _rel(got, ref) < TOL["f32"]
+    del y32, psi
+    shape = qcdgen.site_shape(L) + (3,)
+    chi = g.standard_normal(shape) + 1j * g.standard_normal(shape)
+    ys = _host(lat.stag_apply(_dev(chi), 0.1, prec="f32"))
+    assert _rel(ys, S.apply_staggered(U, chi, 0.1, BC)) < TOL["f32"]
+
+
 @pytest.mark.parametrize("nrhs", [1, 4])
 @pytest.mark.parametrize("split,sblk,swz", [(1, 64, 0), (1, 256, 1), (2, 64, 1), (2, 128, 0), (4, 64, 1), (8, 64, 1)])
 def test_launch_shapes_match_oracle(nrhs, split, sblk, swz):
