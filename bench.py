@@ -2,18 +2,22 @@
 """Benchmark of the Wilson-Dirac CG hot path on one MI355X.
 
 Default workload (one step = one whole solve on data resident in HBM):
-16^3x32 lattice, links U = exp(0.3 i H), Gaussian complex128 source,
-kappa = 0.1365, even-odd preconditioned, plain FP64 CG on D_hat^dag D_hat to
+24^3x48 lattice, links U = exp(0.4 i H), Gaussian complex128 source,
+kappa = 0.137, even-odd preconditioned, plain FP64 CG on D_hat^dag D_hat to
 a true residual of 1e-10.  A step sets the gauge field (conversion into the
-stencil's store), imports the source, runs the CG and exports x.
+stencil's store), imports the source, runs the CG and exports x.  The FP64
+link field (255-382 MB) and the CG vectors exceed the 256 MB Infinity Cache,
+so the stencil streams from HBM.
 
 Printed: one JSON line with the D_W throughput of the step (GFLOP/s at 1320
-flop per stencil output site), the stencil's roofline position (algorithmic
-bytes / measured launch time vs 8 TB/s), time-to-solution, the same solve
-with FP32 and FP16 inner iterations (FP64 reliable updates), and the CPU
-oracle timed on a bounded sample.
+flop per stencil output site), the dominant stencil's roofline position
+(algorithmic bytes / measured launch time vs 8 TB/s), time-to-solution, the
+same solve with FP32 and FP16 inner iterations (recon-12 links, FP64 reliable
+updates), each solution's FP64 true residual recomputed by the CPU oracle,
+the cache-resident 16^3x32 solve beside it, and the oracle timed on the
+host's cores.
 
-Other workloads: --workload cfg1|cfg3|cfg4|cfg5|stencil|pion|force|staggered.
+Other workloads: --workload cfg2|cfg1|cfg4|cfg5|stencil|pion|force|staggered.
 """
 
 import argparse
@@ -214,59 +218,127 @@ def hop_bytes_per_site(prec, recon, mode):
     return 8 * link + sp + epi
 
 
-def cpu_baseline(U, b, kappa, L, budget_s):
-    """The oracle's A_hat = D_hat^dag D_hat applied repeatedly on the host."""
-    import numpy as np
+def host_cpu():
+    """The host's CPU model, sockets, physical cores and the CPUs this process may use."""
+    info = {"model": None, "sockets": None, "physical_cores": None, "logical_cpus": os.cpu_count(),
+            "usable_cpus": len(os.sched_getaffinity(0))}
+    try:
+        import subprocess
+        txt = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        kv = {l.split(":", 1)[0].strip(): l.split(":", 1)[1].strip() for l in txt.splitlines() if ":" in l}
+        info["model"] = kv.get("Model name")
+        if kv.get("Socket(s)", "").isdigit():
+            info["sockets"] = int(kv["Socket(s)"])
+        if info["sockets"] and kv.get("Core(s) per socket", "").isdigit():
+            info["physical_cores"] = info["sockets"] * int(kv["Core(s) per socket"])
+    except (OSError, ValueError):
+        pass
+    if info["physical_cores"] is None:
+        cores = set()
+        phys = None
+        for line in open("/proc/cpuinfo"):
+            k, _, v = line.partition(":")
+            k, v = k.strip(), v.strip()
+            if k == "model name" and not info["model"]:
+                info["model"] = v
+            elif k == "physical id":
+                phys = v
+            elif k == "core id":
+                cores.add((phys, v))
+        info["physical_cores"] = len(cores) or None
+    return info
+
+
+def oracle_threads(host):
+    """Threads for the all-cores oracle timing: the physical cores this process
+    may run on (at most 16, the host share of one GPU on the measurement box)."""
+    n = min(host["usable_cpus"], host["physical_cores"] or host["usable_cpus"])
+    return max(1, min(16, n))
+
+
+def cpu_baseline(U, b, kappa, L, threads):
+    """The oracle's A_hat = D_hat^dag D_hat on the host: one application on one
+    thread, then `threads` applications at once on as many threads (numpy
+    releases the interpreter lock in its array operations; each thread runs
+    the unchanged oracle on its own vector), the throughput of all cores."""
+    from concurrent.futures import ThreadPoolExecutor
     import oracle as O
     e = O.even_mask(L)
     v = b * e
-    n = 0
-    t0 = time.perf_counter()
-    while True:
-        v = O.apply_Ahat(U, v, kappa, BC)
-        v = v / np.linalg.norm(v)
-        n += 1
-        if time.perf_counter() - t0 > budget_s:
-            break
-    dt = time.perf_counter() - t0
     half = (L[0] * L[1] * L[2] * L[3]) // 2
-    flops = n * 4 * FLOP_PER_SITE * half
+    flop = 4 * FLOP_PER_SITE * half
+    t0 = time.perf_counter()
+    O.apply_Ahat(U, v, kappa, BC)
+    t1 = time.perf_counter() - t0
+    vs = [v * (1.0 + 0.01 * k) for k in range(threads)]
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(threads) as ex:
+        list(ex.map(lambda w: O.apply_Ahat(U, w, kappa, BC), vs))
+    tn = time.perf_counter() - t0
+    host = host_cpu()
+    lat = "x".join(map(str, L))
     return {
-        "value": flops / dt / 1e9,
+        "value": threads * flop / tn / 1e9,
         "unit": "GFLOP/s",
-        "cores": 1,
+        "cores": threads,
         "kind": "oracle",
-        "sample": f"{n} applications of the oracle's D_hat^dag D_hat (4 even-odd hops each) on the "
-                  f"{'x'.join(map(str, L))} workload in {dt:.1f} s, numpy FP64 single-threaded",
-        "seconds_per_DdagD": dt / n,
+        "sample": f"{threads} concurrent applications of the oracle's D_hat^dag D_hat (4 even-odd hops each, "
+                  f"numpy FP64) on the {lat} workload, one per thread, in {tn:.1f} s; and one application on "
+                  f"one thread in {t1:.1f} s",
+        "single_thread_gflops": flop / t1 / 1e9,
+        "seconds_per_DdagD_1_thread": t1,
+        "seconds_per_DdagD_all_threads": tn / threads,
+        "host": host,
     }
 
 
-def bench_default(args):
-    import numpy as np
-    import torch
-    from paper_2409_03030_amd import wdirac as W
+def oracle_residuals(U, L, kappa, cases):
+    """err_vs_oracle of each solve: the oracle's FP64 true residual
+    ||b - A_hat x|| / ||b|| of the returned x (threads, one case each)."""
+    from concurrent.futures import ThreadPoolExecutor
+    import oracle as O
+    with ThreadPoolExecutor(len(cases)) as ex:
+        return list(ex.map(lambda xb: float(O.residual_DdagD(U, xb[0], xb[1], kappa, BC, True)), cases))
 
-    log("generating 16^3x32 workload ...")
-    L, width, kappa, U, b = make_workload("cfg2")
-    V = L[0] * L[1] * L[2] * L[3]
-    half = V // 2
+
+# The link-load rule of the stencil launcher: FP64 and FP32 links take the
+# non-temporal hint (kernel hop_kernel_nt) when the launch's link field exceeds
+# 192 MB, or when an FP64 launch moves more than 768 MB.
+def stencil_kernel_name(prec, recon, mode, split, L):
+    half = L[0] * L[1] * L[2] * L[3] // 2
+    link = {"f64": 16, "f32": 8, "f16": 4}[prec] * (9 if recon == 18 else 6)
+    field = 2 * half * 4 * link
+    nt = prec != "f16" and (field > 192e6 or (prec == "f64" and half * hop_bytes_per_site(prec, recon, mode) > 768e6))
+    p = {"f64": 0, "f32": 1, "f16": 2}[prec]
+    return f"void wd::hop_kernel{'_nt' if nt else ''}<{p}, {recon}, {mode}, {split}>"
+
+
+WORKLOAD_TEXT = {
+    "cfg3": "24^3x48 Wilson-Dirac, U=exp(0.4iH), kappa=0.137, even-odd, plain FP64 CG to true residual 1e-10 "
+            "(HBM-resident: the FP64 link field and the CG vectors exceed the 256 MB Infinity Cache)",
+    "cfg2": "16^3x32 Wilson-Dirac, U=exp(0.3iH), kappa=0.1365, even-odd, plain FP64 CG to true residual 1e-10 "
+            "(cache-resident: the working set fits in the 256 MB Infinity Cache)",
+}
+
+
+def solve_workload(args, name, W, torch, tuned):
+    """Plain FP64 CG of one workload as the timed step, then the FP32- and
+    FP16-inner solves and the stencil figures.  Returns (result dict, U, b, x)."""
+    L, width, kappa, U, b = make_workload(name)
+    half = L[0] * L[1] * L[2] * L[3] // 2
     dev = "cuda:0"
     Ud = torch.from_numpy(U).to(dev)
     bd = torch.from_numpy(b).to(dev)
     lat = W.Lattice(L, BC)
     # plain FP64 CG with recon-18 and recon-12 FP64 links (both exact FP64
-    # arithmetic; recon-12 rebuilds the third row, error ~1e-16); the faster
-    # one is the headline
-    tuned = args.tune_file is not None
-    if tuned:
-        W.tune_import(open(args.tune_file).read())
+    # arithmetic; recon-12 rebuilds the third row, error ~1e-16); the one with
+    # the faster stencil is the headline
     links = {}
     for recon in (18, 12):
         lat.set_gauge(Ud, "f64", recon)
         if not tuned:
             sb, sw, sp = lat.autotune("f64", 1)
-            log(f"autotune f64-{recon}: sites/block {sb}, xcd swizzle {sw}, hop split {sp}")
+            log(f"{name} autotune f64-{recon}: sites/block {sb}, xcd swizzle {sw}, hop split {sp}")
         links[recon] = lat.time_hop("f64", 1, n=50)
     recon64 = min(links, key=links.get)
     lat.set_gauge(Ud, "f64", recon64)
@@ -275,22 +347,19 @@ def bench_default(args):
     for prec in ("f32", "f16"):
         if not tuned:
             sb, sw, sp = lat.autotune(prec, 1)
-            log(f"autotune {prec}: sites/block {sb}, xcd swizzle {sw}, hop split {sp}")
-    if args.save_tune:
-        open(args.save_tune, "w").write(W.tune_export())
+            log(f"{name} autotune {prec}: sites/block {sb}, xcd swizzle {sw}, hop split {sp}")
     split64 = next(int(l.split()[9]) for l in W.tune_export().splitlines()
                    if l.split()[:7] == [str(v) for v in (*L, 0, recon64, 1)])
     torch.cuda.synchronize()
 
     plain = W.default_params()  # EO, FP64 inner, tol 1e-10
-    log(f"timing plain FP64 CG (f64 links recon-{recon64}) ...")
+    log(f"{name}: timing plain FP64 CG (f64 links recon-{recon64}) ...")
     x, st, dt = time_solves(lat, Ud, bd, kappa, plain, args.steps, args.warmup, set_gauge=[("f64", recon64)])
     if st["status"] != 0 or st["true_resid"] > 1e-10:
         raise SystemExit(f"plain CG failed: {st}")
-    flops = dw_flops(st, half)
     roof = instrumented(lat, bd, kappa, plain)
-    log(f"plain FP64: {st['iters']} iters, {dt * 1e3:.2f} ms, stencil {roof['achieved_gbs']:.0f} GB/s")
-
+    log(f"{name} plain FP64: {st['iters']} iters, {dt * 1e3:.2f} ms, stencil {roof['achieved_gbs']:.0f} GB/s")
+    xs = {"f64": x}
     mixed = {}
     for inner in ("f32", "f16"):
         p = W.default_params(inner=inner, delta=1e-2)
@@ -298,97 +367,142 @@ def bench_default(args):
         if sm["status"] != 0:
             raise SystemExit(f"{inner} CG failed: {sm}")
         rm = instrumented(lat, bd, kappa, p)
-        err = (torch.linalg.vector_norm(xm - x) / torch.linalg.vector_norm(x)).item()
+        xs[inner] = xm
         mixed[inner] = {
             "time_to_solution_ms": dtm * 1e3,
             "iters": sm["iters"],
             "reliable_updates": sm["reliable_updates"],
             "true_resid": sm["true_resid"],
-            "rel_diff_vs_plain_fp64_x": err,
+            "rel_diff_vs_plain_fp64_x": (torch.linalg.vector_norm(xm - x) / torch.linalg.vector_norm(x)).item(),
             "stencil_gbs": rm["achieved_gbs"],
             "stencil_ms_avg": rm["hop_ms_avg"],
+            "dw_gflops": dw_flops(sm, half) / dtm / 1e9,
             "speedup_vs_plain_fp64": dt / dtm,
         }
-        log(f"{inner} inner: {sm['iters']} iters, {dtm * 1e3:.2f} ms, stencil {rm['achieved_gbs']:.0f} GB/s")
+        log(f"{name} {inner} inner: {sm['iters']} iters, {dtm * 1e3:.2f} ms, stencil {rm['achieved_gbs']:.0f} GB/s")
 
     # The roofline kernel: the stencil variant with the largest share of the
-    # plain FP64 solve (the plain hop, twice per iteration), timed back to back
-    # in the launch shape of the CG; the fused CG-residual stencil beside it.
+    # plain FP64 solve, timed back to back in the launch shape of the CG; the
+    # fused CG-residual stencil beside it.
     dom = roof["dominant_mode"]
     if dom > 2:
         raise SystemExit(f"unexpected dominant stencil mode {dom}")
-    kernel_name = f"void wd::hop_kernel<0, {recon64}, {dom}, {split64}>"
+    lname = "x".join(map(str, L))
+    kernel_name = stencil_kernel_name("f64", recon64, dom, split64, L)
     dom_ms = lat.time_hop("f64", 1, n=200, mode=dom)
     dom_bytes = half * hop_bytes_per_site("f64", recon64, dom)
-    cgr_name = f"void wd::hop_kernel<0, {recon64}, 2, {split64}>"
+    cgr_name = stencil_kernel_name("f64", recon64, 2, split64, L)
     cgr_ms = lat.time_hop("f64", 1, n=200, mode=2)
     cgr_bytes = half * hop_bytes_per_site("f64", recon64, 2)
+    roofline = {
+        "bound": "hbm",
+        "achieved": dom_bytes / (dom_ms * 1e-3) / 1e9,
+        "peak": HBM_PEAK_GBS,
+        "unit": "GB/s",
+        "frac": dom_bytes / (dom_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+        "traffic": lookup_traffic(kernel_name, lname),
+        "kernel": kernel_name,
+        "what": HOP_MODES[dom],
+        "avg_launch_ms": dom_ms,
+        "bytes_per_launch": dom_bytes,
+        "bytes_per_site": dom_bytes / half,
+        "output_sites_per_launch": half,
+        "in_solve": {"by_mode": roof["modes"],
+                     "note": "hipEvents around each launch of one plain FP64 solve (event-to-event, so "
+                             "each launch also carries its dispatch latency)"},
+        "cg_residual_stencil": {
+            "kernel": cgr_name, "avg_launch_ms": cgr_ms, "bytes_per_launch": cgr_bytes,
+            "achieved": cgr_bytes / (cgr_ms * 1e-3) / 1e9,
+            "frac": cgr_bytes / (cgr_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "traffic": lookup_traffic(cgr_name, lname)},
+        "all_stencil_launches": {"achieved_gbs": roof["achieved_gbs"], "avg_launch_ms": roof["hop_ms_avg"],
+                                 "launches": roof["hop_launches"], "gflops": roof["gflops"]},
+    }
+    res = {
+        "workload": WORKLOAD_TEXT[name], "lattice": list(L), "kappa": kappa, "link_width": width,
+        "links": f"f64 recon-{recon64}", "time_to_solution_ms": dt * 1e3, "solves_per_s": 1.0 / dt,
+        "iters": st["iters"], "reliable_updates": st["reliable_updates"], "true_resid": st["true_resid"],
+        "dw_gflops": dw_flops(st, half) / dt / 1e9, "roofline": roofline, "mixed_precision": mixed,
+    }
+    xs = {k: v.cpu().numpy() for k, v in xs.items()}
+    lat.close()
+    del Ud, bd
+    torch.cuda.empty_cache()
+    return res, U, b, xs
+
+
+def bench_default(args):
+    import torch
+    from paper_2409_03030_amd import wdirac as W
+
+    tuned = args.tune_file is not None
+    if tuned:
+        W.tune_import(open(args.tune_file).read())
+    name = args.workload
+    log(f"generating the {name} workload ...")
+    res, U, b, xs = solve_workload(args, name, W, torch, tuned)
+    if args.save_tune:
+        open(args.save_tune, "w").write(W.tune_export())
     copy_gbs = calibration_copy()
     read_gbs = read_bandwidth()
     read128_gbs = read_bandwidth(128 << 20)
+    res["roofline"]["attainable_read_gbs"] = {"1GiB": read_gbs, "128MiB": read128_gbs,
+                                             "note": "plain streaming-read kernel on the same box"}
+    other = None
+    if name == "cfg3" and not args.no_cfg2:
+        log("the cache-resident 16^3x32 workload beside it ...")
+        other, _, _, _ = solve_workload(args, "cfg2", W, torch, tuned)
+    L = tuple(res["lattice"])
+    kappa = res["kappa"]
     cpu = None
     if not args.no_cpu_baseline:
-        log(f"timing the CPU oracle for ~{args.cpu_seconds:.0f} s ...")
-        cpu = cpu_baseline(U, b, kappa, L, args.cpu_seconds)
-        cpu["oracle_time_to_solution_est_s"] = cpu["seconds_per_DdagD"] * (st["iters"] + st["reliable_updates"])
-
+        host = host_cpu()
+        nt = oracle_threads(host)
+        log(f"oracle residuals of the returned solutions and the oracle timing ({nt} threads) ...")
+        errs = oracle_residuals(U, L, kappa, [(xs[k], b) for k in ("f64", "f32", "f16")])
+        res["err_vs_oracle"] = errs[0]
+        res["mixed_precision"]["f32"]["err_vs_oracle"] = errs[1]
+        res["mixed_precision"]["f16"]["err_vs_oracle"] = errs[2]
+        cpu = cpu_baseline(U, b, kappa, L, nt)
+        cpu["oracle_time_to_solution_est_s"] = cpu["seconds_per_DdagD_1_thread"] * (res["iters"] +
+                                                                                     res["reliable_updates"])
+        cpu["oracle_time_to_solution_note"] = ("estimate: CG iterations of the GPU solve x the oracle's time per "
+                                               "D_hat^dag D_hat on one thread (vector updates not counted)")
     out = {
         "metric": METRIC,
-        "value": flops / dt / 1e9,
+        "value": res["dw_gflops"],
         "unit": "GFLOP/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": dt * 1e3,
+        "ms_per_step": res["time_to_solution_ms"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
         "config": {
-            "workload": "16^3x32 Wilson-Dirac, U=exp(0.3iH), kappa=0.1365, even-odd, plain FP64 CG to true residual 1e-10",
+            "workload": res["workload"],
             "lattice": list(L),
             "kappa": kappa,
-            "link_width": width,
+            "link_width": res["link_width"],
             "boundary": "antiperiodic t",
             "precond": "even-odd",
             "inner": "f64",
-            "links": f"f64 recon-{recon64}",
+            "links": res["links"],
         },
-        "time_to_solution_ms": dt * 1e3,
-        "solves_per_s": 1.0 / dt,
-        "iters": st["iters"],
-        "reliable_updates": st["reliable_updates"],
-        "true_resid": st["true_resid"],
-        "roofline": {
-            "bound": "hbm",
-            "achieved": dom_bytes / (dom_ms * 1e-3) / 1e9,
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": dom_bytes / (dom_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
-            "traffic": lookup_traffic(kernel_name, "x".join(map(str, L))),
-            "kernel": kernel_name,
-            "what": HOP_MODES[dom],
-            "avg_launch_ms": dom_ms,
-            "bytes_per_launch": dom_bytes,
-            "bytes_per_site": dom_bytes / half,
-            "in_solve": {"by_mode": roof["modes"],
-                         "note": "hipEvents around each launch of one plain FP64 solve (event-to-event, so "
-                                 "each launch also carries its dispatch latency)"},
-            "cg_residual_stencil": {
-                "kernel": cgr_name, "avg_launch_ms": cgr_ms, "bytes_per_launch": cgr_bytes,
-                "achieved": cgr_bytes / (cgr_ms * 1e-3) / 1e9,
-                "frac": cgr_bytes / (cgr_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
-                "traffic": lookup_traffic(cgr_name, "x".join(map(str, L)))},
-            "all_stencil_launches": {"achieved_gbs": roof["achieved_gbs"], "avg_launch_ms": roof["hop_ms_avg"],
-                                     "launches": roof["hop_launches"], "gflops": roof["gflops"]},
-            "attainable_read_gbs": {"1GiB": read_gbs, "128MiB": read128_gbs,
-                                    "note": "plain streaming-read kernel on the same box"},
-        },
+        "time_to_solution_ms": res["time_to_solution_ms"],
+        "solves_per_s": res["solves_per_s"],
+        "iters": res["iters"],
+        "reliable_updates": res["reliable_updates"],
+        "true_resid": res["true_resid"],
+        "err_vs_oracle": res.get("err_vs_oracle"),
+        "roofline": res["roofline"],
         "copy_1GiB_gbs": copy_gbs,
         "read_1GiB_gbs": read_gbs,
         "read_128MiB_gbs": read128_gbs,
-        "mixed_precision": mixed,
+        "mixed_precision": res["mixed_precision"],
+        "cache_resident_16x16x16x32": other,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
@@ -443,50 +557,6 @@ def bench_cfg1(args):
                         "lattice": list(L), "kappa": kappa},
                        {"time_to_solution_ms": dt * 1e3, "iters": st["iters"], "true_resid": st["true_resid"],
                         "apply_D_ms": d_ms, "note": "latency-bound (128 sites per parity); not a roofline point"})
-
-
-def bench_cfg3(args):
-    """24^3x48, width 0.4, kappa 0.137: FP32 / FP16 inner with recon-12 links, FP64 reliable updates."""
-    import torch
-    from paper_2409_03030_amd import wdirac as W
-    log("generating 24^3x48 workload ...")
-    L, width, kappa, U, b = make_workload("cfg3")
-    half = L[0] * L[1] * L[2] * L[3] // 2
-    Ud, bd = torch.from_numpy(U).cuda(), torch.from_numpy(b).cuda()
-    del U
-    lat = W.Lattice(L, BC)
-    # FP64 links recon-12 (exact to rounding) serve the plain solve and the
-    # reliable updates of the mixed ones
-    for prec, recon in (("f64", 12), ("f32", 12), ("f16", 12)):
-        lat.set_gauge(Ud, prec, recon)
-        sb, sw, sp = lat.autotune(prec, 1)
-        log(f"autotune {prec}: sites/block {sb}, xcd swizzle {sw}, hop split {sp}")
-    res = {}
-    x64 = None
-    for name, p in (("f64", W.default_params()),
-                    ("f32", W.default_params(inner="f32", delta=1e-2)),
-                    ("f16", W.default_params(inner="f16", delta=1e-2))):
-        x, st, dt = time_solves(lat, Ud, bd, kappa, p, args.steps if name != "f64" else max(1, args.steps // 2), 1)
-        if st["status"] != 0:
-            raise SystemExit(f"{name} solve failed: {st}")
-        roof = instrumented(lat, bd, kappa, p)
-        r = {"time_to_solution_ms": dt * 1e3, "iters": st["iters"], "reliable_updates": st["reliable_updates"],
-             "true_resid": st["true_resid"], "stencil_gbs": roof["achieved_gbs"],
-             "stencil_ms_avg": roof["hop_ms_avg"], "dw_gflops": dw_flops(st, half) / dt / 1e9}
-        if x64 is None:
-            x64 = x
-        else:
-            r["rel_diff_vs_fp64_gpu_x"] = (torch.linalg.vector_norm(x - x64) / torch.linalg.vector_norm(x64)).item()
-        res[name] = r
-        log(f"{name}: {st['iters']} iters, {st['reliable_updates']} reliable, {dt * 1e3:.1f} ms, "
-            f"stencil {roof['achieved_gbs']:.0f} GB/s")
-    best = min(("f32", "f16"), key=lambda k: res[k]["time_to_solution_ms"])
-    return _common_out(args, res[best]["dw_gflops"], "GFLOP/s", res[best]["time_to_solution_ms"], best,
-                       {"workload": "24^3x48, U=exp(0.4iH), kappa=0.137, even-odd, mixed-precision CG "
-                                    "(FP32 or FP16 per-site-scaled inner, recon-12, FP64 reliable updates at 1e-2) "
-                                    "to true residual 1e-10", "lattice": list(L), "kappa": kappa, "best_inner": best},
-                       {"solves": res, "speedup_vs_plain_fp64": res["f64"]["time_to_solution_ms"] /
-                        res[best]["time_to_solution_ms"]})
 
 
 def bench_cfg4(args):
@@ -872,9 +942,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="cfg2")
+    ap.add_argument("--workload", default="cfg3")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cfg2", action="store_true", help="default workload: skip the 16^3x32 figures")
     ap.add_argument("--requests", type=int, default=300, help="cfg5: number of served requests")
     ap.add_argument("--rate", type=float, default=50.0, help="cfg5: Poisson arrival rate per second")
     ap.add_argument("--lattice", default="24,24,24,48", help="stencil: lattice extents x,y,z,t")
@@ -892,10 +962,10 @@ def main():
         print(f"bench.py runs on one GPU: the library has no multi-GPU path (asked for --gpus {args.gpus}).",
               file=sys.stderr)
         sys.exit(2)
-    if args.workload == "cfg2":
+    if args.workload in ("cfg2", "cfg3"):
         bench_default(args)
         return
-    fn = {"cfg1": bench_cfg1, "cfg3": bench_cfg3, "cfg4": bench_cfg4, "cfg5": bench_cfg5,
+    fn = {"cfg1": bench_cfg1, "cfg4": bench_cfg4, "cfg5": bench_cfg5,
           "stencil": bench_stencil, "pion": bench_pion, "force": bench_force,
           "staggered": bench_staggered}.get(args.workload)
     if fn is None:

@@ -80,7 +80,9 @@ typedef struct {
   double tol;          /* stop when ||b - A x|| / ||b|| <= tol, true residual in FP64 */
   int32_t maxiter;     /* iteration cap (inner iterations) */
   int32_t inner;       /* wd_prec of the inner CG: F64 = plain FP64 CG, F32/F16 = mixed */
-  int32_t recon;       /* 18 or 12: link storage of the inner operator's gauge store */
+  int32_t recon;       /* 0: use the inner precision's gauge store whatever its recon; 18 or 12: that
+                          store must hold this recon (else WD_ENOGAUGE).  Requests of a batch or
+                          server may mix recons: launches are split by the recon of each store read */
   double delta;        /* reliable update when ||r|| < delta * max ||r|| since the last one;
                           0 = only at convergence (plain CG) */
   int32_t precond;     /* wd_precond */
@@ -157,7 +159,7 @@ wd_status wd_apply_DdagD(wd_lattice lat, void* y, const void* x, int32_t nrhs, d
 /* Workspace bytes for wd_solve_DdagD with these parameters and nrhs fields. */
 size_t wd_solver_workspace_bytes(wd_lattice lat, const wd_solve_params* params, int32_t nrhs);
 
-/* Fill *params with defaults: tol 1e-10, maxiter 100000, inner F64, recon 18,
+/* Fill *params with defaults: tol 1e-10, maxiter 100000, inner F64, recon 0 (any),
  * delta 0, WD_EO, automatic polling, graphs on, timing off, automatic rhs groups. */
 void wd_solve_params_default(wd_solve_params* params);
 

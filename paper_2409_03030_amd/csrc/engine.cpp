@@ -143,12 +143,17 @@ wd_status Engine::run_phase(const std::vector<EItem*>& list, const Phase& ph0) {
   if (ph.prec < 0) ph.prec = p_.inner;
   size_t i = 0;
   while (i < list.size()) {
-    // a launch: consecutive items with the same nrhs, at most kMaxSlots
+    // a launch: consecutive items with the same nrhs and the same link recon
+    // of the store this phase reads (the kernel decodes every slot's links
+    // with one recon), at most kMaxSlots.  Producer and consumer phases of a
+    // folded reduction read the same precision, so they split alike.
     const int nrhs = list[i]->nrhs;
-    size_t j = i;
-    while (j < list.size() && j - i < (size_t)kMaxSlots && list[j]->nrhs == nrhs) ++j;
     const wd_lattice_s* lat0 = list[i]->lat;
     const int recon = lat0->store[ph.prec].recon;
+    size_t j = i;
+    while (j < list.size() && j - i < (size_t)kMaxSlots && list[j]->nrhs == nrhs &&
+           list[j]->lat->store[ph.prec].recon == recon)
+      ++j;
     const Tune t = op_ == OP_STAG ? stag_tune_lookup(lat0, ph.prec, recon, nrhs) : tune_lookup(lat0, ph.prec, recon, nrhs);
     Launch L = base_launch(nrhs, t, ph.parity);
     L.g5in = ph.g5in;

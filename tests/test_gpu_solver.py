@@ -317,3 +317,31 @@ def test_server_multi_rhs_requests():
         assert st12[r]["status"] == 0
         assert _oracle_resid(U, X[r], B[r], 0.13, eo=True) <= TOL
     assert st1[0]["status"] == 0 and _oracle_resid(U, x1, b1, 0.125, eo=True) <= TOL
+
+
+@pytest.mark.parametrize("inner", ["f64", "f32"])
+def test_batch_mixes_link_recons(inner):
+    """Lattices whose FP64 (and inner) stores hold different recons share one
+    batch: each launch takes only slots of one recon, so every result meets
+    the oracle's residual and equals its solve alone bit for bit."""
+    W = _W()
+    cases = [((4, 4, 4, 4), 0.3, 0.12, 18, 12), ((8, 8, 8, 8), 0.4, 0.13, 12, 18),
+             ((4, 6, 8, 10), 0.2, 0.125, 18, 18), ((6, 4, 4, 4), 0.35, 0.128, 12, 12)]
+    reqs, host = [], []
+    for i, (L, w, k, r64, rin) in enumerate(cases):
+        g = qcdgen.rng(800 + i)
+        U = qcdgen.links_exp(L, w, g)
+        b = qcdgen.gaussian_spinor(L, g)
+        stores = [("f64", r64)] + ([("f32", rin)] if inner == "f32" else [])
+        lat = _lattice(L, U, stores)
+        reqs.append((lat, _dev(b), [k]))
+        host.append((U, b, k, lat))
+    p = W.default_params(inner=inner, delta=1e-2 if inner != "f64" else 0.0)
+    res = W.solve_batch(reqs, p)
+    for (x, st), (U, b, k, lat) in zip(res, host):
+        x = _host(x)
+        assert st[0]["status"] == 0
+        assert _oracle_resid(U, x, b, k, eo=True) <= TOL
+        xa, sa = lat.solve(_dev(b), k, p)
+        assert np.array_equal(x, _host(xa))
+        assert st[0]["iters"] == sa[0]["iters"]
