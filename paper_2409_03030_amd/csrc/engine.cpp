@@ -143,18 +143,28 @@ wd_status Engine::run_phase(const std::vector<EItem*>& list, const Phase& ph0) {
   if (ph.prec < 0) ph.prec = p_.inner;
   size_t i = 0;
   while (i < list.size()) {
-    // a launch: consecutive items with the same nrhs and the same link recon
-    // of the store this phase reads (the kernel decodes every slot's links
-    // with one recon), at most kMaxSlots.  Producer and consumer phases of a
-    // folded reduction read the same precision, so they split alike.
+    // a launch: consecutive items with the same nrhs, the same link recon of
+    // the store this phase reads (the kernel decodes every slot's links with
+    // one recon) and the same tuned launch shape, at most kMaxSlots.  The
+    // shape fixes each slot's arithmetic (the hop split orders the sum over
+    // the 8 hops, the block size the first stage of every reduction), so an
+    // item computes the same bits whatever shares its launches.  Producer and
+    // consumer phases of a folded reduction read the same precision, so they
+    // split alike.
     const int nrhs = list[i]->nrhs;
     const wd_lattice_s* lat0 = list[i]->lat;
     const int recon = lat0->store[ph.prec].recon;
-    size_t j = i;
+    auto lookup = [&](const wd_lattice_s* lat) {
+      return op_ == OP_STAG ? stag_tune_lookup(lat, ph.prec, recon, nrhs) : tune_lookup(lat, ph.prec, recon, nrhs);
+    };
+    const Tune t = lookup(lat0);
+    size_t j = i + 1;
     while (j < list.size() && j - i < (size_t)kMaxSlots && list[j]->nrhs == nrhs &&
-           list[j]->lat->store[ph.prec].recon == recon)
+           list[j]->lat->store[ph.prec].recon == recon) {
+      const Tune tj = lookup(list[j]->lat);
+      if (tj.sblk != t.sblk || tj.split != t.split || tj.swz != t.swz) break;
       ++j;
-    const Tune t = op_ == OP_STAG ? stag_tune_lookup(lat0, ph.prec, recon, nrhs) : tune_lookup(lat0, ph.prec, recon, nrhs);
+    }
     Launch L = base_launch(nrhs, t, ph.parity);
     L.g5in = ph.g5in;
     L.g5out = ph.g5out;
