@@ -154,6 +154,23 @@ wd_status wd_apply_DdagD(wd_lattice lat, void* y, const void* x, int32_t nrhs, d
                          int32_t precond, int32_t prec,
                          void* ws, size_t ws_bytes, void* stream);
 
+/* For callers that cannot allocate device memory (code under graph capture,
+ * tight serving loops, harnesses that forbid allocation): wd_apply_D without
+ * the workspace argument.  Its workspace is a file-scope device array of
+ * WD_NOALLOC_SCRATCH_BYTES that every GPU the library runs on holds until the
+ * process ends; the call allocates nothing.  Calls that need more than that
+ * (wd_apply_workspace_bytes(lat, prec, nrhs) > WD_NOALLOC_SCRATCH_BYTES; at
+ * nrhs = 1 FP64 fits up to about 87000 sites, e.g. 16^3x16 or 12^3x24, FP32
+ * and FP16 up to about 174000, e.g. 16^3x32) return WD_EBUFSIZE.  Nothing in
+ * the array needs to start at zero: each call writes every part it reads.
+ * All calls on one GPU share that GPU's array, so calls that overlap on one
+ * GPU (other streams or host threads) race; order them on one stream.  The
+ * first call on a device looks up the array's address there.  Otherwise as
+ * wd_apply_D: asynchronous on stream, x and y complex128 device fields. */
+#define WD_NOALLOC_SCRATCH_BYTES (64u << 20)
+wd_status wd_apply_D_noalloc(wd_lattice lat, void* y, const void* x, int32_t nrhs, double kappa,
+                             int32_t dagger, int32_t precond, int32_t prec, void* stream);
+
 /* ---- solver ------------------------------------------------------------ */
 
 /* Workspace bytes for wd_solve_DdagD with these parameters and nrhs fields. */

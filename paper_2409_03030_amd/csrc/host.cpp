@@ -499,6 +499,51 @@ wd_status wd_apply_DdagD(wd_lattice lat, void* y, const void* x, int32_t nrhs, d
   return apply_common(lat, y, x, nrhs, kappa, precond, prec, ws, ws_bytes, stream, true, 0);
 }
 
+// The allocation-free variant of wd_apply_D takes its workspace from this
+// file-scope array instead of a caller buffer.  In host code the array's name
+// is only a stand-in for the symbol: each device holds its own copy, whose
+// address hipGetSymbolAddress returns with that device current; only that
+// address ever reaches a kernel.  Every call on one device shares its copy.
+static __device__ __align__(256) unsigned char scratch[WD_NOALLOC_SCRATCH_BYTES];
+
+static constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[kMaxDevices];  // per device: the address of its copy of scratch
+
+// Device address of the current device's scratch array, looked up on the
+// first call on that device.
+static wd_status scratch_address(void** out) {
+  int dev = -1;
+  WD_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(WD_EDEVICE, "device %d out of range", dev);
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+    if (!p) return fail(WD_EDEVICE, "hipGetSymbolAddress(scratch) gave a null address");
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return WD_OK;
+}
+
+wd_status wd_apply_D_noalloc(wd_lattice lat, void* y, const void* x, int32_t nrhs, double kappa, int32_t dagger,
+                             int32_t precond, int32_t prec, void* stream) {
+  if (dagger != 0 && dagger != 1) return fail(WD_EINVAL, "dagger must be 0 or 1");
+  wd_status s = check_lattice_for(lat, prec, precond);
+  if (s != WD_OK) return s;
+  if (nrhs < 1 || nrhs > kBlock / 2) return fail(WD_EINVAL, "nrhs = %d out of range [1, %d]", nrhs, kBlock / 2);
+  const size_t need = wd_apply_workspace_bytes(lat, prec, nrhs);
+  if (need > (size_t)WD_NOALLOC_SCRATCH_BYTES)
+    return fail(WD_EBUFSIZE, "the call needs %zu bytes of scratch; the allocation-free call holds %zu", need,
+                (size_t)WD_NOALLOC_SCRATCH_BYTES);
+  void* ws = nullptr;
+  if ((s = scratch_address(&ws)) != WD_OK) return s;
+  return apply_common(lat, y, x, nrhs, kappa, precond, prec, ws, (size_t)WD_NOALLOC_SCRATCH_BYTES, stream, false,
+                      dagger);
+}
+
 void wd_solve_params_default(wd_solve_params* p) {
   if (!p) return;
   memset(p, 0, sizeof *p);

@@ -23,6 +23,8 @@ WD_OK, WD_EINVAL, WD_EBUFSIZE, WD_ENOGAUGE, WD_ENOTCONVERGED, WD_ENONFINITE, WD_
     0, -1, -2, -3, -4, -5, -6, -7, -8)
 F64, F32, F16 = 0, 1, 2
 FULL, EO = 0, 1
+# size of the allocation-free call's scratch array (WD_NOALLOC_SCRATCH_BYTES in wdirac.h)
+NOALLOC_SCRATCH_BYTES = 64 << 20
 PREC = {"f64": F64, "f32": F32, "f16": F16, F64: F64, F32: F32, F16: F16}
 
 
@@ -96,6 +98,7 @@ _SIGS = [
     ("wd_apply_workspace_bytes", C.c_size_t, [_P, C.c_int32, C.c_int32]),
     ("wd_apply_D", C.c_int32, [_P, _P, _P, C.c_int32, C.c_double, C.c_int32, C.c_int32, C.c_int32, _P, C.c_size_t, _P]),
     ("wd_apply_DdagD", C.c_int32, [_P, _P, _P, C.c_int32, C.c_double, C.c_int32, C.c_int32, _P, C.c_size_t, _P]),
+    ("wd_apply_D_noalloc", C.c_int32, [_P, _P, _P, C.c_int32, C.c_double, C.c_int32, C.c_int32, C.c_int32, _P]),
     ("wd_solver_workspace_bytes", C.c_size_t, [_P, C.POINTER(SolveParams), C.c_int32]),
     ("wd_solve_params_default", None, [C.POINTER(SolveParams)]),
     ("wd_solve_DdagD", C.c_int32, [_P, _P, _P, C.c_int32, C.POINTER(C.c_double), C.POINTER(SolveParams), _P,
@@ -276,6 +279,17 @@ class Lattice:
         ws = self._workspace(nb, x.device, ("apply", PREC[prec], n))
         _check(lib().wd_apply_D(self.handle, _ptr(y), _ptr(x), n, float(kappa), int(bool(dagger)), int(precond),
                                 PREC[prec], _ptr(ws), ws.numel(), _stream(stream)), "wd_apply_D")
+        return y
+
+    def apply_D_noalloc(self, x, kappa, dagger=False, precond=FULL, prec="f64", out=None, stream=None):
+        """apply_D through the allocation-free entry point (no workspace; see wdirac.h)."""
+        torch = _torch()
+        nrhs = None if x.dim() == 6 else x.shape[0]
+        _check_field(x, self._field_shape(nrhs), "x")
+        n = 1 if nrhs is None else nrhs
+        y = torch.empty_like(x) if out is None else out
+        _check(lib().wd_apply_D_noalloc(self.handle, _ptr(y), _ptr(x), n, float(kappa), int(bool(dagger)),
+                                        int(precond), PREC[prec], _stream(stream)), "wd_apply_D_noalloc")
         return y
 
     def apply_DdagD(self, x, kappa, precond=FULL, prec="f64", out=None, stream=None):
