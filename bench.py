@@ -806,7 +806,12 @@ def bench_staggered(args):
 
 
 def bench_cfg5(args):
-    """Served stream: Poisson arrivals at 50/s over four lattice sizes, continuous batching."""
+    """Served stream: Poisson arrivals at 50/s over four lattice sizes, continuous
+    batching.  The requests arriving in the first warmup_s seconds are served
+    but not counted; latency percentiles and throughput come from the next
+    `requests` arrivals.  The offered load rho = lambda E[S] takes E[S] from
+    each request's solve alone (its field's alone time at three kappa,
+    interpolated in kappa)."""
     import threading
     import numpy as np
     import torch
@@ -825,60 +830,96 @@ def bench_cfg5(args):
                 lat.set_gauge(U, prec, recon)
             del U
             fields.append((lat, w))
-    n_req = args.requests
     rate = args.rate
-    arrivals = np.cumsum(g.exponential(1.0 / rate, n_req))
-    picks = [(fields[int(g.integers(0, len(fields)))], float(g.uniform(0.12, 0.136))) for _ in range(n_req)]
+    n_warm = int(round(args.warmup_s * rate))
+    n_req = args.requests
+    n_tot = n_warm + n_req
+    arrivals = np.cumsum(g.exponential(1.0 / rate, n_tot))
+    pick_f = [int(g.integers(0, len(fields))) for _ in range(n_tot)]
+    pick_k = [float(g.uniform(0.12, 0.136)) for _ in range(n_tot)]
     sources = {}
-    for (lat, _), _k in picks:
+    for fi in pick_f:
+        lat = fields[fi][0]
         if lat.L not in sources:
             sources[lat.L] = [torch.from_numpy(qcdgen.gaussian_spinor(lat.L, g)).cuda() for _ in range(4)]
     torch.cuda.synchronize()
+    kgrid = (0.12, 0.128, 0.136)
+
+    def service_times(params):
+        """Alone solve time of each field at the kappa grid (median of 3)."""
+        t = []
+        for lat, _ in fields:
+            b = sources[lat.L][0]
+            row = []
+            for k in kgrid:
+                lat.solve(b, k, params)
+                ts = []
+                for _ in range(3):
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    lat.solve(b, k, params)
+                    torch.cuda.synchronize()
+                    ts.append(time.perf_counter() - t0)
+                row.append(float(np.median(ts)))
+            t.append(row)
+        return t
 
     def run(params, label):
+        talone = service_times(params)
+        es = float(np.mean([np.interp(pick_k[i], kgrid, talone[pick_f[i]]) for i in range(n_warm, n_tot)]))
         free, total = torch.cuda.mem_get_info()
         pool = int(min(24 << 30, free * 0.5))
         srv = W.Server(pool, max_slots=16, params=params)
-        lat_s = []
         done = {}
-        t_start = time.perf_counter()
         tickets = []
+        t_start = time.perf_counter()
 
         def submit_all():
-            for i in range(n_req):
-                (lat, w), kappa = picks[i]
+            for i in range(n_tot):
+                lat = fields[pick_f[i]][0]
                 while time.perf_counter() - t_start < arrivals[i]:
                     time.sleep(0.0002)
                 b = sources[lat.L][i % 4]
-                t = srv.submit(lat, b, kappa)
-                tickets.append((t, i, time.perf_counter() - t_start))
+                t = srv.submit(lat, b, pick_k[i])
+                tickets.append((t, i))
         th = threading.Thread(target=submit_all)
         th.start()
         pending = {}
         k = 0
-        while len(done) < n_req:
+        while len(done) < n_tot:
             while k < len(tickets):
-                t, i, ts = tickets[k]
-                pending[t] = (i, ts)
+                t, i = tickets[k]
+                pending[t] = i
                 k += 1
             for t in list(pending):
                 r = srv.poll(t)
                 if r is not None:
-                    i, ts = pending.pop(t)
-                    x, st = r
-                    done[i] = (ts, time.perf_counter() - t_start, st[0])
+                    i = pending.pop(t)
+                    done[i] = (time.perf_counter() - t_start, r[1][0])
             time.sleep(0.0005)
         th.join()
-        t_end = max(v[1] for v in done.values())
         srv.close()
-        lat_ms = np.array([(v[1] - arrivals[i]) * 1e3 for i, v in done.items()])
-        ok = all(v[2]["status"] == 0 for v in done.values())
-        resid = max(v[2]["true_resid"] for v in done.values())
-        out = {"requests": n_req, "offered_rate_per_s": rate, "p50_ms": float(np.percentile(lat_ms, 50)),
-               "p99_ms": float(np.percentile(lat_ms, 99)), "mean_ms": float(lat_ms.mean()),
-               "solves_per_s": n_req / t_end, "all_converged": ok, "max_true_resid": resid,
-               "wall_s": t_end}
-        log(f"{label}: p50 {out['p50_ms']:.1f} ms, p99 {out['p99_ms']:.1f} ms, {out['solves_per_s']:.1f} solves/s")
+        meas = range(n_warm, n_tot)
+        lat_ms = np.array([(done[i][0] - arrivals[i]) * 1e3 for i in meas])
+        t_first = arrivals[n_warm]
+        t_last = max(done[i][0] for i in meas)
+        ok = all(done[i][1]["status"] == 0 for i in range(n_tot))
+        resid = max(done[i][1]["true_resid"] for i in range(n_tot))
+        by_size = {}
+        for i in meas:
+            key = "x".join(map(str, fields[pick_f[i]][0].L))
+            by_size.setdefault(key, []).append((done[i][0] - arrivals[i]) * 1e3)
+        out = {"requests_measured": n_req, "warmup_requests": n_warm, "warmup_s": args.warmup_s,
+               "offered_rate_per_s": rate, "mean_alone_service_ms": es * 1e3, "offered_load_rho": rate * es,
+               "p50_ms": float(np.percentile(lat_ms, 50)), "p99_ms": float(np.percentile(lat_ms, 99)),
+               "mean_ms": float(lat_ms.mean()), "max_ms": float(lat_ms.max()),
+               "solves_per_s": n_req / (t_last - t_first), "all_converged": ok, "max_true_resid": resid,
+               "alone_ms_by_field": {"x".join(map(str, fields[f][0].L)) + f"#{f}": [v * 1e3 for v in talone[f]]
+                                     for f in range(len(fields))},
+               "p50_p99_ms_by_size": {kk: [float(np.percentile(v, 50)), float(np.percentile(v, 99))]
+                                      for kk, v in sorted(by_size.items())}}
+        log(f"{label}: rho {out['offered_load_rho']:.2f}, p50 {out['p50_ms']:.1f} ms, p99 {out['p99_ms']:.1f} ms, "
+            f"{out['solves_per_s']:.1f} solves/s")
         return out
 
     mixed = run(W.default_params(inner="f16", delta=1e-2), "served, FP16 inner")
@@ -888,7 +929,8 @@ def bench_cfg5(args):
     return _common_out(args, best["solves_per_s"], "solves/s", best["mean_ms"], "f16" if best is mixed else "f32",
                        {"workload": f"served stream: Poisson arrivals at {rate}/s, lattices uniform over "
                                     "{8^4, 12^3x24, 16^3x32, 24^3x48}, kappa U[0.12,0.136], link width U[0.2,0.5], "
-                                    "Gaussian sources, each to 1e-10, admission by HBM footprint",
+                                    "Gaussian sources, each to 1e-10, admission by HBM footprint; "
+                                    f"{n_req} requests measured after a {args.warmup_s:g} s warm-up",
                         "requests": n_req},
                        {"served_fp16_inner": mixed, "served_fp32_inner": mixed32, "served_plain_fp64": plain,
                         "p99_ms": best["p99_ms"], "p50_ms": best["p50_ms"]})
@@ -945,7 +987,8 @@ def main():
     ap.add_argument("--workload", default="cfg3")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-cfg2", action="store_true", help="default workload: skip the 16^3x32 figures")
-    ap.add_argument("--requests", type=int, default=300, help="cfg5: number of served requests")
+    ap.add_argument("--requests", type=int, default=2000, help="cfg5: served requests measured after the warm-up")
+    ap.add_argument("--warmup-s", type=float, default=10.0, help="cfg5: seconds of arrivals served but not measured")
     ap.add_argument("--rate", type=float, default=50.0, help="cfg5: Poisson arrival rate per second")
     ap.add_argument("--lattice", default="24,24,24,48", help="stencil: lattice extents x,y,z,t")
     ap.add_argument("--save-tune", default=None, help="write the tuning table to this file")

@@ -376,8 +376,9 @@ wd_status wd_time_hop(wd_lattice lat, int32_t prec, int32_t nrhs, int32_t mode, 
 wd_status wd_time_read(const void* buf, size_t bytes, int32_t n, void* out, size_t out_bytes, double* ms_per_read,
                        void* stream);
 
-/* Autotune the stencil launch shape (sites per workgroup, XCD-aware block
- * order, number of threads the 8 hops of a site are split over) for this
+/* Autotune the stencil launch shape (sites per workgroup, block order: 0
+ * plain, 1 each XCD a contiguous range of sites, 2 the same ranges visited
+ * t-slice innermost; number of threads the 8 hops of a site are split over) for this
  * lattice, precision and nrhs by timing every candidate on stream.  Among
  * the candidates whose workgroup count lets the CG fold its reductions (if
  * any do), of those within 3 % of the fastest, the one with the fewest
@@ -392,7 +393,7 @@ wd_status wd_autotune(wd_lattice lat, int32_t prec, int32_t nrhs, void* ws, size
                       void* stream);
 
 /* Read or write the tuning table as text ("Lx Ly Lz Lt prec recon nrhs sblk swz split"
- * lines; split in {1,2,4,8} (8 not at FP64); split * sblk * nrhs <= 256, or <= 512
+ * lines; swz in {0,1,2}; split in {1,2,4,8} (8 not at FP64); split * sblk * nrhs <= 256, or <= 512
  * for split 8; sblk * nrhs >= 64).
  * wd_tune_export returns the bytes needed (including the NUL) and writes at
  * most cap bytes into buf (may be NULL). */

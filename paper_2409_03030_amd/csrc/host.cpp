@@ -96,7 +96,7 @@ bool valid_tune(const Tune& t, int nrhs, int prec) {
   const int sb = t.sblk;
   if (sb < 1 || (sb & (sb - 1)) != 0) return false;
   if (t.split != 1 && t.split != 2 && t.split != 4 && t.split != 8) return false;
-  if (t.swz != 0 && t.swz != 1) return false;
+  if (t.swz < 0 || t.swz > 2) return false;
   const int per = sb * nrhs;
   if (per < 64 || t.split * per > (t.split == 8 ? kMaxBlock : kBlock)) return false;
   if (t.split > 1 && per % 64 != 0) return false;
@@ -153,6 +153,12 @@ void finish_launch(Launch& L) {
     b += L.s[i].nblk;
   }
   L.total_blocks = b;
+  L.bt = 0;
+  if (L.swz == 2 && L.nslots == 1 && L.parity != 2) {
+    const Geom& g = L.s[0].g;
+    const int per_slice = g.n / g.L[3];  // sites of one parity in a t-slice
+    if (per_slice % L.sblk == 0) L.bt = per_slice / L.sblk;
+  }
 }
 
 Launch base_launch(int nrhs, const Tune& t, int parity) {
@@ -288,27 +294,46 @@ wd_status check_lattice_for(const wd_lattice_s* lat, int prec, int precond) {
 // one kernel is read from the same L2 by the next (staggered FP32 solve 5.6
 // against 5.9 ms, FP16-inner Wilson solve 10.1 against 10.5 ms, with bare
 // stencil times within noise of each other).
+// The swz = 2 order differs from swz = 1 only when the blocks of a parity
+// split over the 8 XCDs into ranges of at least two whole t-slices.
+bool tslice_order_applies(const Geom& g, int sblk) {
+  const int per_slice = g.n / g.L[3];
+  if (per_slice % sblk) return false;
+  const int bt = per_slice / sblk, nb = (g.n + sblk - 1) / sblk;
+  if (nb % 8) return false;
+  const int q = nb / 8;
+  return q % bt == 0 && q / bt >= 2;
+}
+
 Tune pick_shape(const std::vector<std::pair<Tune, double>>& timed_all, long long n, int nrhs, int per_iter,
                 double vec_bytes, Tune fallback) {
   constexpr double kTuneSlack = 1.03;
-  // The XCD-aware order of a (sblk, split) pair is kept unless it is more than
-  // kSwzSlack slower than the plain order in the bare stencil, which times one
-  // kernel alone and so misses the cross-kernel L2 reuse; that reuse needs a
-  // vector to fit in half of the XCDs' L2s (8 x 4 MB), otherwise only a tie
-  // goes to the XCD-aware order.
+  // For each (sblk, split) one candidate goes on: the faster of the XCD-aware
+  // orders (swz 1 and 2, which give every XCD the same range of sites), kept
+  // unless it is more than swz_slack slower than the plain order in the bare
+  // stencil.  The bare stencil times one kernel alone and so misses the
+  // cross-kernel L2 reuse of the XCD-aware orders; that reuse needs a vector to
+  // fit in half of the XCDs' L2s (8 x 4 MB), otherwise only a tie goes to them.
   const double swz_slack = vec_bytes <= 16.0e6 ? 1.10 : 1.0;
   std::vector<std::pair<Tune, double>> timed;
   for (const auto& c : timed_all) {
-    const std::pair<Tune, double>* other = nullptr;
-    for (const auto& d : timed_all)
-      if (d.first.sblk == c.first.sblk && d.first.split == c.first.split && d.first.swz != c.first.swz) other = &d;
-    if (!other) {
-      timed.push_back(c);
-    } else if (c.first.swz == 1) {
-      if (c.second <= swz_slack * other->second) timed.push_back({c.first, std::min(c.second, other->second)});
-    } else if (other->second > swz_slack * c.second) {
-      timed.push_back(c);
+    bool first = true;  // first candidate of its (sblk, split) in the list
+    for (const auto& d : timed_all) {
+      if (&d == &c) break;
+      if (d.first.sblk == c.first.sblk && d.first.split == c.first.split) first = false;
     }
+    if (!first) continue;
+    const std::pair<Tune, double>* plain = nullptr;
+    const std::pair<Tune, double>* xcd = nullptr;
+    for (const auto& d : timed_all) {
+      if (d.first.sblk != c.first.sblk || d.first.split != c.first.split) continue;
+      if (d.first.swz == 0) plain = &d;
+      else if (!xcd || d.second < xcd->second) xcd = &d;
+    }
+    if (!xcd) timed.push_back(*plain);
+    else if (!plain) timed.push_back(*xcd);
+    else if (xcd->second <= swz_slack * plain->second) timed.push_back({xcd->first, std::min(xcd->second, plain->second)});
+    else timed.push_back(*plain);
   }
   auto blocks_of = [&](const Tune& t) { return (n + t.sblk - 1) / t.sblk; };
   auto folds = [&](const Tune& t) {
@@ -329,8 +354,8 @@ Tune pick_shape(const std::vector<std::pair<Tune, double>>& timed_all, long long
     const double cc = cost(c);
     if (cc > kTuneSlack * best) continue;
     const long long b = blocks_of(c.first);
-    const bool better = bt_blocks < 0 || b < bt_blocks ||
-                        (b == bt_blocks && (c.first.swz > bt.swz || (c.first.swz == bt.swz && cc < bt_cost)));
+    const bool cx = c.first.swz != 0, bx = bt.swz != 0;
+    const bool better = bt_blocks < 0 || b < bt_blocks || (b == bt_blocks && (cx > bx || (cx == bx && cc < bt_cost)));
     if (better) {
       bt = c.first;
       bt_blocks = b;
@@ -764,9 +789,11 @@ wd_status wd_autotune(wd_lattice lat, int32_t prec, int32_t nrhs, void* ws, size
   std::vector<std::pair<Tune, double>> timed;
   for (int split = 1; split <= 8; split *= 2) {
     for (int sblk = 1; sblk <= kMaxBlock; sblk *= 2) {
-      for (int swz = 0; swz <= 1; ++swz) {
+      for (int swz = 0; swz <= 2; ++swz) {
         Tune t{sblk, swz, split};
         if (!valid_tune(t, nrhs, prec)) continue;
+        // the t-slice order exists only where the XCD ranges are whole t-slices
+        if (swz == 2 && !tslice_order_applies(lat->g, sblk)) continue;
         WD_HIP(hipMemsetAsync(w + 2 * vb, 0, vb, st));
         // the best of 3 timings of 20 launches: the shapes of a small lattice
         // differ by a few percent, about the run-to-run spread of one timing

@@ -42,7 +42,7 @@ inline int acc_prec(int prec) { return prec == F16 ? F32 : prec; }
 
 struct Tune {
   int sblk;   // sites per block (power of two; see valid_tune)
-  int swz;    // XCD-aware block order
+  int swz;    // block order: 0 plain, 1 XCD-aware, 2 XCD-aware with t-slices innermost
   int split;  // threads per (site, rhs) in the stencil: 1, 2 or 4
 };
 bool valid_tune(const Tune& t, int nrhs, int prec);
@@ -67,6 +67,8 @@ constexpr long long kFoldReads = 1LL << 19;
 // partial per block), preferring the XCD-aware order, which is also kept
 // within 10 % of the plain order while a vector (vec_bytes) fits in half of
 // the L2s.
+// Whether the swz = 2 block order differs from swz = 1 on this lattice at sblk sites per block.
+bool tslice_order_applies(const Geom& g, int sblk);
 Tune pick_shape(const std::vector<std::pair<Tune, double>>& timed, long long n, int nrhs, int per_iter,
                 double vec_bytes, Tune fallback);
 Tune tune_lookup(const wd_lattice_s* lat, int prec, int recon, int nrhs);

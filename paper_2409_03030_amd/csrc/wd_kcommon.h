@@ -18,21 +18,35 @@ struct Tile {
 };
 
 // Workgroups are dealt to the 8 XCDs round robin (w -> XCD w % 8).  With
-// swizzling, XCD x receives a contiguous range of logical blocks so that
-// neighbouring sites share that XCD's L2.
-__device__ __forceinline__ int logical_block(int w, int nb, int swz) {
+// swz = 1, XCD x receives a contiguous range of logical blocks so that
+// neighbouring sites share that XCD's L2.  With swz = 2 the XCD keeps the same
+// range (so vectors written by one kernel are read from the same L2 by the
+// next) but visits it in another order: the range spans S whole t-slices of bt
+// blocks, and the k-th block the XCD runs is block k / S of slice k % S.  The
+// t-neighbours of a site are then read within a few dozen blocks of each
+// other rather than a whole slice apart, which keeps them in the L2 between
+// their uses (at 24^3x48 it cut the FP64 stencil's fetched bytes from 1.37 to
+// 1.10 times the algorithmic ones).  A range that is not whole slices keeps
+// the swz = 1 order.
+__device__ __forceinline__ int logical_block(int w, int nb, int swz, int bt) {
   if (!swz) return w;
   const int q = nb >> 3, rem = nb & 7;
   const int x = w & 7;
   const int start = x * q + (x < rem ? x : rem);
-  return start + (w >> 3);
+  const int k = w >> 3;
+  if (swz == 2 && bt > 0) {
+    const int cnt = q + (x < rem ? 1 : 0);
+    const int S = cnt / bt;
+    if (S >= 2 && S * bt == cnt) return start + (k % S) * bt + k / S;
+  }
+  return start + k;
 }
 
 // lead: workgroups at the start of the grid that take no tile (they finish the
 // previous launch's reduction).
 __device__ __forceinline__ Tile make_tile(const Launch& L, int lead = 0) {
   Tile t;
-  const int b = logical_block((int)blockIdx.x - lead, L.total_blocks, L.swz);
+  const int b = logical_block((int)blockIdx.x - lead, L.total_blocks, L.swz, L.bt);
   int sl = 0;
 #pragma unroll 1
   for (int i = 1; i < L.nslots; ++i)

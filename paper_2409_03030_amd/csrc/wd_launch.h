@@ -80,7 +80,9 @@ struct Launch {
                         // work: by one extra workgroup per slot at the start of a Wilson stencil's grid, by
                         // block 0 of each slot in a staggered stencil, by every block for FIN_CG (CG vector
                         // update) and FIN_ALPHA_ALL (staggered residual update)
-  int swz;              // 1: XCD-aware block order
+  int swz;              // block order: 0 plain, 1 XCD-aware, 2 XCD-aware with the t-slices of an XCD's range
+                        // visited innermost (see logical_block)
+  int bt;               // swz 2: blocks per t-slice of the launch's only slot; 0 = order as swz 1
   int total_blocks;
   double coef;          // epilogue coefficient when no RhsState is attached
   double coef2;         // second coefficient (staggered XPAY) when no RhsState is attached

@@ -297,3 +297,37 @@ def test_autotune_shapes_and_solve():
         for r in range(4):
             assert st[r]["status"] == 0, (inner, r)
             assert O.residual_DdagD(U, xh[r], psi[r], 0.1365, BC, True) <= 1e-10, (inner, r)
+
+
+@pytest.mark.parametrize("nrhs", [1, 4])
+@pytest.mark.parametrize("split", [1, 2, 4])
+def test_tslice_block_order(nrhs, split):
+    """The XCD order that visits each XCD's t-slices innermost (swz 2) gives the
+    oracle's D_hat, bitwise the same as the plain XCD order with the same split,
+    and solves through it meet the oracle's residual.  8x4x8x16 at 64 sites per
+    block has 2 blocks per t-slice and 2 slices per XCD range, so the order
+    really differs from swz 1."""
+    W = _W()
+    L = (8, 4, 8, 16)   # dims used by no other test: the tuning table is process-wide
+    sb = 64 // nrhs
+    g = qcdgen.rng(141)
+    U = qcdgen.links_exp(L, 0.4, g)
+    psi = qcdgen.gaussian_spinor(L, g, nrhs)
+    lat = _lattice(L, U, [("f64", 12), ("f32", 12), ("f16", 12)])
+    e = O.even_mask(L)
+    out = {}
+    for swz in (1, 2):
+        lines = "".join(f"{L[0]} {L[1]} {L[2]} {L[3]} {p} 12 {nrhs} {sb} {swz} {split}\n" for p in (0, 1, 2))
+        W.tune_import(lines)
+        for prec in ("f64", "f32", "f16"):
+            y = _host(lat.apply_D(_dev(psi), 0.1365, precond=1, prec=prec))
+            out[(swz, prec)] = y
+            for r in range(nrhs):
+                assert _rel(y[r], O.apply_Dhat(U, psi[r] * e, 0.1365, BC)) < TOL[prec]
+    for prec in ("f64", "f32", "f16"):
+        assert np.array_equal(out[(1, prec)], out[(2, prec)]), prec
+    b = np.ascontiguousarray(psi[0])
+    for inner in ("f64", "f16"):
+        x, st = lat.solve(_dev(b), 0.1365, W.default_params(inner=inner, delta=1e-2 if inner != "f64" else 0.0))
+        assert st[0]["status"] == 0, inner
+        assert O.residual_DdagD(U, _host(x), b, 0.1365, BC, True) <= 1e-10, inner
