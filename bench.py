@@ -947,7 +947,7 @@ def bench_stencil(args):
     lat = W.Lattice(L, BC)
     half = L[0] * L[1] * L[2] * L[3] // 2
     res = {}
-    for prec, recon in (("f64", 18), ("f64", 12), ("f32", 12), ("f16", 12)):
+    for prec, recon in (("f64", 18), ("f64", 12), ("f32", 18), ("f32", 12), ("f16", 18), ("f16", 12)):
         lat.set_gauge(U, prec, recon)
         sb, sw, sp = lat.autotune(prec, 1)
         ms = lat.time_hop(prec, 1, n=args.steps * 20)
