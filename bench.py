@@ -17,7 +17,7 @@ updates), each solution's FP64 true residual recomputed by the CPU oracle,
 the cache-resident 16^3x32 solve beside it, and the oracle timed on the
 host's cores.
 
-Other workloads: --workload cfg2|cfg1|cfg4|cfg5|stencil|pion|force|staggered.
+Other workloads: --workload cfg2|cfg1|cfg4|cfg5|stencil|pion|force|staggered|oracle.
 """
 
 import argparse
@@ -560,7 +560,9 @@ def bench_cfg1(args):
 
 
 def bench_cfg4(args):
-    """16^3x32, 12 point sources per kappa in one batched solve (FP32 inner, FP64 outer)."""
+    """16^3x32, 12 point sources per kappa in one batched solve (FP32 inner, FP64 outer).
+    --rhs-group G solves the 12 sources as 12/G slots of G right-hand sides in
+    the same launches (0: the library's default)."""
     import torch
     import qcdgen
     from paper_2409_03030_amd import wdirac as W
@@ -569,12 +571,14 @@ def bench_cfg4(args):
     Ud = torch.from_numpy(U).cuda()
     B = torch.from_numpy(qcdgen.point_sources(L)).cuda()
     lat = W.Lattice(L, BC)
+    G = args.rhs_group if args.rhs_group > 0 else 4
     for prec, recon in (("f64", 18), ("f32", 12)):
         lat.set_gauge(Ud, prec, recon)
-        for nrhs in (1, 4):   # 12-rhs requests run as three 4-rhs slots (rhs_group)
+        for nrhs in sorted({1, G}):
             sb, sw, sp = lat.autotune(prec, nrhs)
             log(f"autotune {prec} nrhs {nrhs}: sites/block {sb}, swizzle {sw}, split {sp}")
-    p = W.default_params(inner="f32", delta=1e-2)
+    p = W.default_params(inner="f32", delta=1e-2, rhs_group=args.rhs_group)
+    p1 = W.default_params(inner="f32", delta=1e-2)
     res = {}
     tot_batched = tot_single = 0.0
     flops = 0.0
@@ -588,7 +592,7 @@ def bench_cfg4(args):
         tb = (time.perf_counter() - t0) / args.steps
         t0 = time.perf_counter()
         for r in range(12):
-            lat.solve(B[r].contiguous(), kappa, p)
+            lat.solve(B[r].contiguous(), kappa, p1)
         torch.cuda.synchronize()
         ts = time.perf_counter() - t0
         its = [s["iters"] for s in st]
@@ -616,17 +620,33 @@ def bench_cfg4(args):
               "iters_by_kappa": {str(k): [s["iters"] for s, kk in zip(st36, k36) if kk == k][:1][0]
                                  for k in (0.130, 0.134, 0.1365)}}
     log(f"36 rhs, mixed kappa, one solve: {t36 * 1e3:.1f} ms vs three 12-rhs solves {tot_batched * 1e3:.1f} ms")
-    roof = None
+    # The 12-rhs stencil against the roofline: the plain hop H_oe over all 12
+    # sources (one launch of 12/G slots), event-timed inside one solve, against
+    # the algorithmic bytes of 12 sources sharing one read of the links:
+    # 8 FP32-12 links (384 B) per site plus 12 x (96 B in + 96 B out), i.e.
+    # 224 B per site and source.
     pt = W.SolveParams.from_buffer_copy(p)
     pt.timing = 1
     X, st = lat.solve(B, [0.1365] * 12, pt)
     s0 = st[0]
-    roof = {"stencil_gbs": s0["hop_bytes"] / (s0["hop_ms"] * 1e-3) / 1e9,
-            "stencil_ms_avg": s0["hop_ms"] / max(1, s0["hop_launches"])}
+    m0 = s0["hop_inner_mode_launches"][0]
+    ms0 = s0["hop_inner_mode_ms"][0] / max(1, m0)
+    ideal = half * (8 * 48 + 12 * 192)
+    roof = {"bound": "hbm", "what": "FP32 plain hop H_oe over the 12 sources, event-timed in the solve (each "
+                                     "launch also carries its dispatch latency; launches that skipped converged "
+                                     "sources included)",
+            "avg_launch_ms": ms0, "bytes_per_launch_12rhs_links_once": ideal, "bytes_per_site_rhs": ideal / half / 12,
+            "achieved": ideal / (ms0 * 1e-3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": ideal / (ms0 * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "library_bytes_per_launch": s0["hop_inner_mode_bytes"][0] / max(1, m0),
+            "note": f"{12 // G} slot(s) of {G} sources: the library's own count reads the links once per slot",
+            "all_stencil_launches_gbs": s0["hop_bytes"] / (s0["hop_ms"] * 1e-3) / 1e9,
+            "cache_resident": "the 16^3x32 FP32 link field (25 MB) and the 12-source vectors (about 190 MB) fit "
+                              "in the 256 MB Infinity Cache"}
     return _common_out(args, flops / tot_batched / 1e9, "GFLOP/s", tot_batched / 3 * 1e3, "f32",
                        {"workload": "16^3x32, 12 spin-colour point sources per kappa in one batched CG launch, "
                                     "kappa in {0.130, 0.134, 0.1365}, complex64 inner / complex128 outer",
-                        "lattice": list(L), "nrhs": 12},
+                        "lattice": list(L), "nrhs": 12, "rhs_group": G},
                        {"per_kappa": res, "speedup_batched_vs_sequential": tot_single / tot_batched,
                         "mixed_kappa_36rhs": stress, "stencil_12rhs": roof})
 
@@ -979,6 +999,76 @@ def bench_stencil(args):
                        {"stencil": res})
 
 
+def bench_oracle(args):
+    """The CPU oracle on every workload lattice, on this host's cores: one
+    D_hat^dag D_hat (D^dag D on the full 4^4 lattice) on one thread, the
+    throughput of one application per thread on all physical cores, and
+    oracle CG solves to 1e-10 where they take seconds (4^4 unpreconditioned,
+    8^4 even-odd); the longer solves are estimated as iterations x time per
+    application (iterations from the GPU solves of the same workloads)."""
+    from concurrent.futures import ThreadPoolExecutor
+    import numpy as np
+    import oracle as O
+    import qcdgen
+    host = host_cpu()
+    nt = oracle_threads(host)
+    cases = [("cfg1 4^4 Haar, unpreconditioned", (4, 4, 4, 4), "haar", 0.12, False, qcdgen.CONFIG_SEED_BASE),
+             ("cfg5 8^4", (8, 8, 8, 8), 0.35, 0.128, True, 7),
+             ("cfg5 12^3x24", (12, 12, 12, 24), 0.35, 0.128, True, 8),
+             ("cfg2/cfg4 16^3x32", (16, 16, 16, 32), 0.3, 0.1365, True, qcdgen.CONFIG_SEED_BASE + 1),
+             ("cfg3 24^3x48", (24, 24, 24, 48), 0.4, 0.137, True, qcdgen.CONFIG_SEED_BASE + 2)]
+    res = {}
+    for label, L, w, kappa, eo, seed in cases:
+        g = qcdgen.rng(seed)
+        U = qcdgen.links_haar(L, g) if w == "haar" else qcdgen.links_exp(L, w, g)
+        b = qcdgen.gaussian_spinor(L, g)
+        V = L[0] * L[1] * L[2] * L[3]
+        if eo:
+            v = b * O.even_mask(L)
+            op = lambda x: O.apply_Ahat(U, x, kappa, BC)
+            flop = 4 * FLOP_PER_SITE * (V // 2)
+        else:
+            v = b
+            op = lambda x: O.apply_DdagD(U, x, kappa, BC)
+            flop = 2 * FLOP_PER_SITE * V
+        ts = []
+        t_all = time.perf_counter()
+        while len(ts) < 5 and (not ts or time.perf_counter() - t_all < 20.0):
+            t0 = time.perf_counter()
+            op(v)
+            ts.append(time.perf_counter() - t0)
+        t1 = float(np.median(ts))
+        vs = [v * (1.0 + 0.01 * k) for k in range(nt)]
+        t0 = time.perf_counter()
+        with ThreadPoolExecutor(nt) as ex:
+            list(ex.map(op, vs))
+        tn = time.perf_counter() - t0
+        r = {"lattice": list(L), "kappa": kappa, "operator": "D_hat^dag D_hat (even-odd)" if eo else "D^dag D (full)",
+             "seconds_1_thread": t1, "gflops_1_thread": flop / t1 / 1e9,
+             "threads": nt, "gflops_all_threads": nt * flop / tn / 1e9}
+        if V <= 4096:
+            t0 = time.perf_counter()
+            x, info = O.solve_DdagD(U, b, kappa, BC, eo=eo)
+            r["cg_to_1e-10_seconds"] = time.perf_counter() - t0
+            r["cg_iterations"] = info["iters"]
+            r["cg_true_residual"] = float(O.residual_DdagD(U, x, b, kappa, BC, eo))
+        res[label] = r
+        log(f"oracle {label}: {t1:.3f} s per application on 1 thread ({r['gflops_1_thread']:.3f} GFLOP/s), "
+            f"{r['gflops_all_threads']:.2f} GFLOP/s on {nt} threads"
+            + (f", CG {r['cg_iterations']} iterations in {r['cg_to_1e-10_seconds']:.1f} s" if "cg_iterations" in r else ""))
+    # time-to-solution estimates from the GPU solves' iteration counts (74 at
+    # 24^3x48, 151 at 16^3x32 plain FP64; one application per iteration)
+    est = {"cfg3 24^3x48": 74 + 1, "cfg2/cfg4 16^3x32": 151 + 1}
+    for k, it in est.items():
+        res[k]["cg_to_1e-10_estimate_s_1_thread"] = it * res[k]["seconds_1_thread"]
+    top = res["cfg3 24^3x48"]
+    return _common_out(args, top["gflops_all_threads"], "GFLOP/s", top["seconds_1_thread"] * 1e3, "f64",
+                       {"workload": "the CPU oracle (numpy FP64) on every workload lattice, on the host's cores"},
+                       {"host": host, "by_lattice": res,
+                        "note": "CPU only; the 50 solves/s served stream is far beyond the oracle (a 24^3x48 "
+                                "solve alone takes minutes on one thread)"})
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -991,6 +1081,7 @@ def main():
     ap.add_argument("--warmup-s", type=float, default=10.0, help="cfg5: seconds of arrivals served but not measured")
     ap.add_argument("--rate", type=float, default=50.0, help="cfg5: Poisson arrival rate per second")
     ap.add_argument("--lattice", default="24,24,24,48", help="stencil: lattice extents x,y,z,t")
+    ap.add_argument("--rhs-group", type=int, default=0, help="cfg4: sources per slot (0: library default)")
     ap.add_argument("--save-tune", default=None, help="write the tuning table to this file")
     ap.add_argument("--tune-file", default=None, help="load this tuning table instead of autotuning")
     ap.add_argument("--stag-shape", default=None,
@@ -1008,7 +1099,7 @@ def main():
     if args.workload in ("cfg2", "cfg3"):
         bench_default(args)
         return
-    fn = {"cfg1": bench_cfg1, "cfg4": bench_cfg4, "cfg5": bench_cfg5,
+    fn = {"cfg1": bench_cfg1, "cfg4": bench_cfg4, "oracle": bench_oracle, "cfg5": bench_cfg5,
           "stencil": bench_stencil, "pion": bench_pion, "force": bench_force,
           "staggered": bench_staggered}.get(args.workload)
     if fn is None:

@@ -114,6 +114,11 @@ typedef struct {
   double hop_mode_ms[4];
   int64_t hop_mode_launches[4];
   double hop_mode_bytes[4];
+  /* the same split, counting only the stencil launches at the inner precision (for a mixed solve:
+     without the FP64 launches of the reliable updates) */
+  double hop_inner_mode_ms[4];
+  int64_t hop_inner_mode_launches[4];
+  double hop_inner_mode_bytes[4];
 } wd_solve_stats;
 
 /* ---- lattice ---------------------------------------------------------- */

@@ -228,7 +228,7 @@ wd_status Engine::run_phase(const std::vector<EItem*>& list, const Phase& ph0) {
       if (e != hipSuccess) return hip_fail(e, "stencil launch");
       const double bytes = op_ == OP_STAG ? stag_launch_bytes(ph.prec, recon, ph.mode, sites, nrhs)
                                           : hop_launch_bytes(ph.prec, recon, ph.mode, sites, nrhs);
-      e = timer_ ? timer_->end(stream_, sites, bytes, op_ == OP_STAG ? 0 : ph.mode) : hipSuccess;
+      e = timer_ ? timer_->end(stream_, sites, bytes, (op_ == OP_STAG ? 0 : ph.mode) + 4 * ph.prec) : hipSuccess;
       if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
     } else {
       hipError_t e = op_ == OP_STAG ? launch_sblas(L, ph.prec, ph.mode, stream_)
@@ -664,9 +664,10 @@ wd_status run_batch(std::vector<EItem>& items, const wd_solve_params& p, RhsStat
     return result;
   }
   const double hop_ms = timer.on ? timer.total_ms() : 0.0;
-  double mms[4], mb[4];
-  long long mn[4];
+  double mms[4], mb[4], ims[4], ib[4];
+  long long mn[4], in[4];
   timer.by_mode(mms, mn, mb);
+  timer.by_mode(ims, in, ib, p.inner);
   wd_status worst = WD_OK;
   for (size_t q = 0; q < nst; ++q) {
     wd_status st = stats_from_state(fin[q], secs, &timer, stats[q]);
@@ -675,6 +676,9 @@ wd_status run_batch(std::vector<EItem>& items, const wd_solve_params& p, RhsStat
       stats[q].hop_mode_ms[m] = mms[m];
       stats[q].hop_mode_launches[m] = mn[m];
       stats[q].hop_mode_bytes[m] = mb[m];
+      stats[q].hop_inner_mode_ms[m] = ims[m];
+      stats[q].hop_inner_mode_launches[m] = in[m];
+      stats[q].hop_inner_mode_bytes[m] = ib[m];
     }
     if (worst == WD_OK && st != WD_OK) worst = st;
   }

@@ -199,7 +199,7 @@ hipError_t HopTimer::end(hipStream_t s, long long sites, double b, int m) {
   return r;
 }
 
-void HopTimer::by_mode(double ms[4], long long n[4], double b[4]) {
+void HopTimer::by_mode(double ms[4], long long n[4], double b[4], int prec) {
   for (int m = 0; m < 4; ++m) {
     ms[m] = 0.0;
     n[m] = 0;
@@ -209,6 +209,7 @@ void HopTimer::by_mode(double ms[4], long long n[4], double b[4]) {
     float t = 0.f;
     if (hipEventElapsedTime(&t, ev[i], ev[i + 1]) != hipSuccess) continue;
     const int m = mode[i / 2] & 3;
+    if (prec >= 0 && (mode[i / 2] >> 2) != prec) continue;
     ms[m] += t;
     n[m] += 1;
     b[m] += mode_bytes[i / 2];

@@ -90,12 +90,13 @@ struct HopTimer {
   size_t used = 0;
   long long site_updates = 0;
   double bytes = 0.0;
-  std::vector<int> mode;          // epilogue mode of each timed launch
+  std::vector<int> mode;          // epilogue mode + 4 x precision of each timed launch
   std::vector<double> mode_bytes;  // its algorithmic bytes
   hipError_t begin(hipStream_t s);
   hipError_t end(hipStream_t s, long long sites, double bytes, int mode);
   double total_ms();
-  void by_mode(double ms[4], long long n[4], double b[4]);
+  // per epilogue mode; prec >= 0: only the launches at that precision
+  void by_mode(double ms[4], long long n[4], double b[4], int prec = -1);
   void release();
 };
 

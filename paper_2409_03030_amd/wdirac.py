@@ -65,6 +65,9 @@ class SolveStats(C.Structure):
         ("hop_mode_ms", C.c_double * 4),
         ("hop_mode_launches", C.c_int64 * 4),
         ("hop_mode_bytes", C.c_double * 4),
+        ("hop_inner_mode_ms", C.c_double * 4),
+        ("hop_inner_mode_launches", C.c_int64 * 4),
+        ("hop_inner_mode_bytes", C.c_double * 4),
     ]
 
     def as_dict(self):
