@@ -47,12 +47,17 @@ __device__ __forceinline__ int logical_block(int w, int nb, int swz, int bt) {
 __device__ __forceinline__ Tile make_tile(const Launch& L, int lead = 0) {
   Tile t;
   const int b = logical_block((int)blockIdx.x - lead, L.total_blocks, L.swz, L.bt);
-  int sl = 0;
+  int sl = 0, lb;
+  if (L.ilv) {
+    sl = b % L.nslots;
+    lb = b / L.nslots;
+  } else {
 #pragma unroll 1
-  for (int i = 1; i < L.nslots; ++i)
-    if (b >= L.s[i].blk0) sl = i;
+    for (int i = 1; i < L.nslots; ++i)
+      if (b >= L.s[i].blk0) sl = i;
+    lb = b - L.s[sl].blk0;
+  }
   const Slot& S = L.s[sl];
-  int lb = b - S.blk0;
   t.slot = sl;
   t.lblk = lb;
   if (L.parity == 2) {
