@@ -574,6 +574,8 @@ def bench_cfg4(args):
     G = args.rhs_group if args.rhs_group > 0 else 4
     for prec, recon in (("f64", 18), ("f32", 12)):
         lat.set_gauge(Ud, prec, recon)
+        if args.tune_file:
+            continue
         for nrhs in sorted({1, G}):
             sb, sw, sp = lat.autotune(prec, nrhs)
             log(f"autotune {prec} nrhs {nrhs}: sites/block {sb}, swizzle {sw}, split {sp}")
@@ -1099,12 +1101,19 @@ def main():
     if args.workload in ("cfg2", "cfg3"):
         bench_default(args)
         return
+    if args.tune_file:
+        from paper_2409_03030_amd import wdirac as W
+        W.tune_import(open(args.tune_file).read())
     fn = {"cfg1": bench_cfg1, "cfg4": bench_cfg4, "oracle": bench_oracle, "cfg5": bench_cfg5,
           "stencil": bench_stencil, "pion": bench_pion, "force": bench_force,
           "staggered": bench_staggered}.get(args.workload)
     if fn is None:
         raise SystemExit(f"unknown workload {args.workload}")
-    print(json.dumps(fn(args)), flush=True)
+    out = fn(args)
+    if args.save_tune:
+        from paper_2409_03030_amd import wdirac as W
+        open(args.save_tune, "w").write(W.tune_export())
+    print(json.dumps(out), flush=True)
 
 
 if __name__ == "__main__":

@@ -157,6 +157,11 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2409_03030_amd.build`")
+        # torch first: its wheel carries its own HIP runtime, and the library
+        # must bind to that one.  Loaded the other way round, the process holds
+        # two HIP runtimes and a kernel launched through one is unknown to the
+        # other ("invalid device function").
+        _torch()
         L = C.CDLL(LIB_PATH)
         for name, res, args in _SIGS:
             f = getattr(L, name)
