@@ -19,13 +19,102 @@ namespace wd {
 
 template <int P> struct AccOf { static constexpr int value = P == F16 ? F32 : P; };
 
+// The split stencil's parts finish the output together when each part's
+// share (12 / D components) is whole 16-byte chunks: FP64 with 2 or 4 parts,
+// FP32 with 2.  Otherwise (FP16, whose per-site scale needs all 24 reals in
+// one thread; FP32 with 4 parts; 8 parts) part 0 finishes the whole site.
+template <int P, int D> struct SplitEpilogue {
+  static constexpr bool value = (P == F64 && (D == 2 || D == 4)) || (P == F32 && D == 2);
+};
+
+// Components c0 .. c0+NK-1 of a spinor (NK = 12: the whole spinor, any format).
+template <int P, int NK, typename T>
+__device__ __forceinline__ void load_comps(const void* base, size_t ne, size_t e, int c0, cplx<T>* s) {
+  if constexpr (NK == 12) {
+    spinor<T> sp;
+    SpinorFmt<P>::load(base, ne, e, sp);
+#pragma unroll
+    for (int k = 0; k < 12; ++k) s[k] = sp.c[k];
+  } else {
+    SpinorFmt<P>::template load_comps<NK>(base, ne, e, c0, s);
+  }
+}
+
+template <int P, int NK, typename T>
+__device__ __forceinline__ void store_comps(void* base, size_t ne, size_t e, int c0, const cplx<T>* s) {
+  if constexpr (NK == 12) {
+    spinor<T> sp;
+#pragma unroll
+    for (int k = 0; k < 12; ++k) sp.c[k] = s[k];
+    SpinorFmt<P>::store(base, ne, e, sp);
+  } else {
+    SpinorFmt<P>::template store_comps<NK>(base, ne, e, c0, s);
+  }
+}
+
+// The epilogue on components c0 .. c0+NK-1 of the site's H in (h, after the
+// optional gamma5): stores them and returns their part of the launch's norm.
+template <int P, int A, int MODE, int NK, typename T>
+__device__ __forceinline__ double hop_epilogue_comps(const Launch& L, const Slot& S, const Tile& t, bool both,
+                                                     int par, size_t ne, size_t e, int c0, const cplx<T>* h) {
+  using TA = typename RealOf<A>::T;
+  if constexpr (MODE == HOP_PLAIN) {
+    char* out = (char*)S.out + (both ? (size_t)par * S.vstride : 0);
+    store_comps<P, NK>(out, ne, e, c0, h);
+    return 0.0;
+  } else {
+    const T c = (T)(S.st ? S.st[t.rhs].c : L.coef);
+    const char* aux = (const char*)S.aux + (both ? (size_t)par * S.vstride : 0);
+    cplx<T> a[NK];
+    load_comps<P, NK>(aux, ne, e, c0, a);
+#pragma unroll
+    for (int k = 0; k < NK; ++k) {
+      a[k].re -= c * h[k].re;
+      a[k].im -= c * h[k].im;
+    }
+    double v = 0.0;
+    if constexpr (MODE == HOP_XPAY) {
+      char* out = (char*)S.out + (both ? (size_t)par * S.vstride : 0);
+      store_comps<P, NK>(out, ne, e, c0, a);
+#pragma unroll
+      for (int k = 0; k < NK; ++k) v += (double)a[k].re * (double)a[k].re + (double)a[k].im * (double)a[k].im;
+    } else if constexpr (MODE == HOP_CGR) {
+      const TA alpha = (TA)S.st[t.rhs].alpha;
+      char* r = (char*)S.r + (both ? (size_t)par * S.astride : 0);
+      cplx<TA> rv[NK];
+      load_comps<A, NK>(r, ne, e, c0, rv);
+#pragma unroll
+      for (int k = 0; k < NK; ++k) {
+        rv[k].re -= alpha * (TA)a[k].re;
+        rv[k].im -= alpha * (TA)a[k].im;
+      }
+      store_comps<A, NK>(r, ne, e, c0, rv);
+#pragma unroll
+      for (int k = 0; k < NK; ++k) v += (double)rv[k].re * (double)rv[k].re + (double)rv[k].im * (double)rv[k].im;
+    } else {  // HOP_RESID, FP64 only
+      const char* b = (const char*)S.b + (both ? (size_t)par * S.hstride : 0);
+      char* rh = (char*)S.rh + (both ? (size_t)par * S.hstride : 0);
+      cplx<double> bv[NK], res[NK];
+      load_comps<F64, NK>(b, ne, e, c0, bv);
+#pragma unroll
+      for (int k = 0; k < NK; ++k) {
+        res[k].re = bv[k].re - (double)a[k].re;
+        res[k].im = bv[k].im - (double)a[k].im;
+      }
+      store_comps<F64, NK>(rh, ne, e, c0, res);
+#pragma unroll
+      for (int k = 0; k < NK; ++k) v += res[k].re * res[k].re + res[k].im * res[k].im;
+    }
+    return v;
+  }
+}
+
 // NT: links read with the non-temporal hint (hop_kernel_nt, FP64 and FP32),
 // for launches whose links cannot stay in the Infinity Cache (stream_links).
 template <int P, int R, int MODE, int D, bool NT>
 __device__ __forceinline__ void hop_body(const Launch& L) {
   using T = typename RealOf<P>::T;
   constexpr int A = AccOf<P>::value;
-  using TA = typename RealOf<A>::T;
   // The previous launch's reduction is finished by nslots extra workgroups at
   // the start of the grid, one per slot, while the others run the stencil:
   // this launch's own work must not depend on it (its mask reads only states
@@ -53,81 +142,100 @@ __device__ __forceinline__ void hop_body(const Launch& L) {
     const char* in = (const char*)S.in + (both ? (size_t)(1 - par) * S.vstride : 0);
     hop_part<P, R, D, NT>(S.g, par, t.site, t.rhs, L.nrhs, S.gauge, in, S.bc, L.g5in != 0, t.part, acc);
   }
-  if (D > 1) {
-    // parts 1..D-1 hand their sums to part 0, which adds them in part order
-    constexpr int kLds = D > 1 ? (D - 1) * 24 * ((D == 8 ? kMaxBlock : kBlock) / D) : 1;
-    __shared__ T lds_acc[kLds];
+  double v = 0.0;
+  if constexpr (SplitEpilogue<P, D>::value) {
+    // Each part finishes 12/D of the site's components: part p takes the
+    // other parts' sums of its components from LDS and adds all D in part
+    // order (the same sums as one thread adding whole spinors), then loads,
+    // combines and stores only its own chunks.
+    constexpr int NK = 12 / D;
+    __shared__ T lds_acc[(D - 1) * 24 * (kBlock / D)];
     const int per = L.sblk * L.nrhs;
-    const int loc = (int)threadIdx.x - t.part * per;
-    if (sel && t.part > 0) {
-      T* q = lds_acc + (size_t)(t.part - 1) * 24 * per + loc;
+    const int p = t.part;
+    const int loc = (int)threadIdx.x - p * per;
+    // writer q, owner o != q: block q * (D - 1) + (o < q ? o : o - 1) of 2 NK reals
+    auto blk = [&](int q, int o) { return lds_acc + (size_t)((q * (D - 1) + (o < q ? o : o - 1)) * 2 * NK) * per + loc; };
+    if (sel) {
 #pragma unroll
-      for (int k = 0; k < 12; ++k) {
-        q[(2 * k) * per] = acc.c[k].re;
-        q[(2 * k + 1) * per] = acc.c[k].im;
+      for (int o = 0; o < D; ++o) {
+        if (o == p) continue;
+        T* d = blk(p, o);
+#pragma unroll
+        for (int k = 0; k < NK; ++k) {
+          d[(2 * k) * per] = acc.c[o * NK + k].re;
+          d[(2 * k + 1) * per] = acc.c[o * NK + k].im;
+        }
       }
     }
     __syncthreads();
+    if (sel) {
+      cplx<T> mine[NK], h[NK];
+#pragma unroll
+      for (int o = 0; o < D; ++o)
+        if (o == p) {
+#pragma unroll
+          for (int k = 0; k < NK; ++k) mine[k] = acc.c[o * NK + k];
+        }
+#pragma unroll
+      for (int q = 0; q < D; ++q) {
+        cplx<T> x[NK];
+        if (q == p) {
+#pragma unroll
+          for (int k = 0; k < NK; ++k) x[k] = mine[k];
+        } else {
+          const T* src = blk(q, p);
+#pragma unroll
+          for (int k = 0; k < NK; ++k) x[k] = {src[(2 * k) * per], src[(2 * k + 1) * per]};
+        }
+#pragma unroll
+        for (int k = 0; k < NK; ++k) {
+          if (q == 0) h[k] = x[k];
+          else h[k] = cadd(h[k], x[k]);
+        }
+      }
+      const int c0 = p * NK;
+      if (L.g5out) {
+#pragma unroll
+        for (int k = 0; k < NK; ++k)
+          if (c0 + k >= 6) h[k] = cneg(h[k]);
+      }
+      v = hop_epilogue_comps<P, A, MODE, NK>(L, S, t, both, par, ne, e, c0, h);
+    }
+    if (L.fin != FIN_NONE) block_reduce_store(L, S, t, v, D);
+  } else {
+    if (D > 1) {
+      // parts 1..D-1 hand their sums to part 0, which adds them in part order
+      constexpr int kLds = D > 1 ? (D - 1) * 24 * ((D == 8 ? kMaxBlock : kBlock) / D) : 1;
+      __shared__ T lds_acc[kLds];
+      const int per = L.sblk * L.nrhs;
+      const int loc = (int)threadIdx.x - t.part * per;
+      if (sel && t.part > 0) {
+        T* q = lds_acc + (size_t)(t.part - 1) * 24 * per + loc;
+#pragma unroll
+        for (int k = 0; k < 12; ++k) {
+          q[(2 * k) * per] = acc.c[k].re;
+          q[(2 * k + 1) * per] = acc.c[k].im;
+        }
+      }
+      __syncthreads();
+      if (sel && t.part == 0) {
+#pragma unroll
+        for (int pp = 1; pp < D; ++pp) {
+          const T* q = lds_acc + (size_t)(pp - 1) * 24 * per + loc;
+#pragma unroll
+          for (int k = 0; k < 12; ++k) {
+            acc.c[k].re += q[(2 * k) * per];
+            acc.c[k].im += q[(2 * k + 1) * per];
+          }
+        }
+      }
+    }
     if (sel && t.part == 0) {
-#pragma unroll
-      for (int pp = 1; pp < D; ++pp) {
-        const T* q = lds_acc + (size_t)(pp - 1) * 24 * per + loc;
-#pragma unroll
-        for (int k = 0; k < 12; ++k) {
-          acc.c[k].re += q[(2 * k) * per];
-          acc.c[k].im += q[(2 * k + 1) * per];
-        }
-      }
+      if (L.g5out) gamma5_inplace(acc);
+      v = hop_epilogue_comps<P, A, MODE, 12>(L, S, t, both, par, ne, e, 0, acc.c);
     }
+    if (L.fin != FIN_NONE) block_reduce_store(L, S, t, v);
   }
-  double v = 0.0;
-  if (sel && t.part == 0) {
-    if (L.g5out) gamma5_inplace(acc);
-    if (MODE == HOP_PLAIN) {
-      char* out = (char*)S.out + (both ? (size_t)par * S.vstride : 0);
-      SpinorFmt<P>::store(out, ne, e, acc);
-    } else {
-      const T c = (T)(S.st ? S.st[t.rhs].c : L.coef);
-      const char* aux = (const char*)S.aux + (both ? (size_t)par * S.vstride : 0);
-      spinor<T> a;
-      SpinorFmt<P>::load(aux, ne, e, a);
-#pragma unroll
-      for (int k = 0; k < 12; ++k) {
-        a.c[k].re -= c * acc.c[k].re;
-        a.c[k].im -= c * acc.c[k].im;
-      }
-      if (MODE == HOP_XPAY) {
-        char* out = (char*)S.out + (both ? (size_t)par * S.vstride : 0);
-        SpinorFmt<P>::store(out, ne, e, a);
-        v = spinor_norm2(a);
-      } else if (MODE == HOP_CGR) {
-        const TA alpha = (TA)S.st[t.rhs].alpha;
-        char* r = (char*)S.r + (both ? (size_t)par * S.astride : 0);
-        spinor<TA> rv;
-        SpinorFmt<A>::load(r, ne, e, rv);
-#pragma unroll
-        for (int k = 0; k < 12; ++k) {
-          rv.c[k].re -= alpha * (TA)a.c[k].re;
-          rv.c[k].im -= alpha * (TA)a.c[k].im;
-        }
-        SpinorFmt<A>::store(r, ne, e, rv);
-        v = spinor_norm2(rv);
-      } else {  // HOP_RESID, FP64 only
-        const char* b = (const char*)S.b + (both ? (size_t)par * S.hstride : 0);
-        char* rh = (char*)S.rh + (both ? (size_t)par * S.hstride : 0);
-        spinor<double> bv, res;
-        SpinorFmt<F64>::load(b, ne, e, bv);
-#pragma unroll
-        for (int k = 0; k < 12; ++k) {
-          res.c[k].re = bv.c[k].re - (double)a.c[k].re;
-          res.c[k].im = bv.c[k].im - (double)a.c[k].im;
-        }
-        SpinorFmt<F64>::store(rh, ne, e, res);
-        v = spinor_norm2(res);
-      }
-    }
-  }
-  if (L.fin != FIN_NONE) block_reduce_store(L, S, t, v);
 }
 
 template <int P, int R, int MODE, int D>

@@ -96,6 +96,20 @@ template <> struct SpinorFmt<F64> {
 #pragma unroll
     for (int k = 0; k < 12; ++k) v[k * ne + e] = make_double2(s.c[k].re, s.c[k].im);
   }
+  // components c0 .. c0+NK-1 only
+  template <int NK> WD_HD static void load_comps(const void* base, size_t ne, size_t e, int c0, cplx<double>* s) {
+    const double2* v = (const double2*)base;
+#pragma unroll
+    for (int k = 0; k < NK; ++k) {
+      const double2 d = v[(size_t)(c0 + k) * ne + e];
+      s[k] = {d.x, d.y};
+    }
+  }
+  template <int NK> WD_HD static void store_comps(void* base, size_t ne, size_t e, int c0, const cplx<double>* s) {
+    double2* v = (double2*)base;
+#pragma unroll
+    for (int k = 0; k < NK; ++k) v[(size_t)(c0 + k) * ne + e] = make_double2(s[k].re, s[k].im);
+  }
 };
 
 template <> struct SpinorFmt<F32> {
@@ -115,6 +129,24 @@ template <> struct SpinorFmt<F32> {
 #pragma unroll
     for (int k = 0; k < 6; ++k)
       v[k * ne + e] = make_float4(s.c[2 * k].re, s.c[2 * k].im, s.c[2 * k + 1].re, s.c[2 * k + 1].im);
+  }
+  // components c0 .. c0+NK-1 only (c0 and NK even: whole chunks)
+  template <int NK> WD_HD static void load_comps(const void* base, size_t ne, size_t e, int c0, cplx<float>* s) {
+    static_assert(NK % 2 == 0, "whole chunks");
+    const float4* v = (const float4*)base;
+#pragma unroll
+    for (int k = 0; k < NK / 2; ++k) {
+      const float4 d = v[(size_t)(c0 / 2 + k) * ne + e];
+      s[2 * k] = {d.x, d.y};
+      s[2 * k + 1] = {d.z, d.w};
+    }
+  }
+  template <int NK> WD_HD static void store_comps(void* base, size_t ne, size_t e, int c0, const cplx<float>* s) {
+    static_assert(NK % 2 == 0, "whole chunks");
+    float4* v = (float4*)base;
+#pragma unroll
+    for (int k = 0; k < NK / 2; ++k)
+      v[(size_t)(c0 / 2 + k) * ne + e] = make_float4(s[2 * k].re, s[2 * k].im, s[2 * k + 1].re, s[2 * k + 1].im);
   }
 };
 

@@ -205,12 +205,15 @@ __device__ void finalize_rhs(int fin, RhsState& s, double sum) {
 // device-scope release fence per block -- on gfx950 a write-back of the
 // XCD's whole L2 -- or coherent stores, waits and atomics whose round trips
 // serialise at the end of every block; both cost more than a small kernel.)
+// parts: how many part-major groups of sblk * nrhs threads hold values (a
+// stencil whose split parts each finish a share of the output components);
+// the tree then runs over parts * sblk "sites".
 // All threads of the block must call this.
-__device__ void block_reduce_store(const Launch& L, const Slot& S, const Tile& t, double v) {
+__device__ void block_reduce_store(const Launch& L, const Slot& S, const Tile& t, double v, int parts = 1) {
   __shared__ double lds[kMaxBlock];
   const int tid = (int)threadIdx.x;
   const int nr = L.nrhs;
-  const int sb = L.sblk;
+  const int sb = L.sblk * parts;
   const int nthr = sb * nr;
   const int sl = tid / nr;
   if (nr == 1) {

@@ -82,7 +82,8 @@ struct Launch {
                         // update) and FIN_ALPHA_ALL (staggered residual update)
   int swz;              // block order: 0 plain, 1 XCD-aware, 2 XCD-aware with the t-slices of an XCD's range
                         // visited innermost (see logical_block)
-  int bt;               // swz 2: blocks per t-slice of the launch's only slot; 0 = order as swz 1
+  int bt;               // swz 2: logical blocks per t-slice (of the only slot, or of all interleaved groups);
+                        // 0 = order as swz 1
   int ilv;              // 1: the slots are right-hand-side groups of one lattice (same geometry, links and
                         // block count); logical block b is block b / nslots of slot b % nslots, so the
                         // groups' blocks for the same sites run next to each other (links read from the L2)

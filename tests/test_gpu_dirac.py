@@ -331,3 +331,19 @@ def test_tslice_block_order(nrhs, split):
         x, st = lat.solve(_dev(b), 0.1365, W.default_params(inner=inner, delta=1e-2 if inner != "f64" else 0.0))
         assert st[0]["status"] == 0, inner
         assert O.residual_DdagD(U, _host(x), b, 0.1365, BC, True) <= 1e-10, inner
+    if nrhs != 4:
+        return
+    # 8 sources as 2 groups of 4 in the same launches (interleaved slots): the
+    # t-slice order then spans both groups' blocks
+    b8 = qcdgen.gaussian_spinor(L, g, 8)
+    xs = {}
+    for swz in (1, 2):
+        W.tune_import("".join(f"{L[0]} {L[1]} {L[2]} {L[3]} {p} 12 4 {sb} {swz} {split}\n" for p in (0, 1)))
+        par = W.default_params(inner="f32", delta=1e-2)
+        par.rhs_group = 4
+        x, st = lat.solve(_dev(b8), 0.1365, par)
+        assert all(s["status"] == 0 for s in st), swz
+        xs[swz] = _host(x)
+    assert np.array_equal(xs[1], xs[2])
+    for r in range(8):
+        assert O.residual_DdagD(U, xs[2][r], b8[r], 0.1365, BC, True) <= 1e-10, r
