@@ -21,8 +21,10 @@ template <int P> struct AccOf { static constexpr int value = P == F16 ? F32 : P;
 
 // The split stencil's parts finish the output together when each part's
 // share (12 / D components) is whole 16-byte chunks: FP64 with 2 or 4 parts,
-// FP32 with 2.  Otherwise (FP16, whose per-site scale needs all 24 reals in
-// one thread; FP32 with 4 parts; 8 parts) part 0 finishes the whole site.
+// FP32 with 2.  Otherwise part 0 finishes the whole site: FP16, whose
+// per-site scale needs all 24 reals (a variant exchanging each half's largest
+// component through LDS was 5 % slower), FP32 with 4 parts (half-chunk
+// accesses: faster at 24^3x48, slower at 16^3x32), and 8 parts.
 template <int P, int D> struct SplitEpilogue {
   static constexpr bool value = (P == F64 && (D == 2 || D == 4)) || (P == F32 && D == 2);
 };
@@ -119,9 +121,16 @@ __device__ __forceinline__ void hop_body(const Launch& L) {
   // the start of the grid, one per slot, while the others run the stencil:
   // this launch's own work must not depend on it (its mask reads only states
   // that the finalize step leaves unchanged for the selected rhs).
+  // LDS: the parts' exchange of sums, which the finalize-only workgroups use
+  // for their stage-2 sums instead, and the block reduction's buffer.
+  constexpr int kThreads = D == 8 ? kMaxBlock : kBlock;
+  constexpr size_t kAccBytes = D > 1 ? (size_t)(D - 1) * 24 * (kThreads / D) * sizeof(T) : 0;
+  constexpr size_t kRawBytes = kAccBytes > kRedSlots * sizeof(double) ? kAccBytes : kRedSlots * sizeof(double);
+  __shared__ __align__(16) unsigned char lds_raw[kRawBytes];
+  __shared__ double lds_red[kThreads];
   const int lead = L.prefin != FIN_NONE ? L.nslots : 0;
   if ((int)blockIdx.x < lead) {
-    gather_and_finalize(L, L.s[blockIdx.x], L.prefin);
+    gather_and_finalize_buf(L, L.s[blockIdx.x], L.prefin, (double*)lds_raw);
     return;
   }
   const Tile t = make_tile(L, lead);
@@ -149,7 +158,7 @@ __device__ __forceinline__ void hop_body(const Launch& L) {
     // order (the same sums as one thread adding whole spinors), then loads,
     // combines and stores only its own chunks.
     constexpr int NK = 12 / D;
-    __shared__ T lds_acc[(D - 1) * 24 * (kBlock / D)];
+    T* lds_acc = (T*)lds_raw;
     const int per = L.sblk * L.nrhs;
     const int p = t.part;
     const int loc = (int)threadIdx.x - p * per;
@@ -201,12 +210,11 @@ __device__ __forceinline__ void hop_body(const Launch& L) {
       }
       v = hop_epilogue_comps<P, A, MODE, NK>(L, S, t, both, par, ne, e, c0, h);
     }
-    if (L.fin != FIN_NONE) block_reduce_store(L, S, t, v, D);
+    if (L.fin != FIN_NONE) block_reduce_store_buf(L, S, t, v, D, lds_red);
   } else {
     if (D > 1) {
       // parts 1..D-1 hand their sums to part 0, which adds them in part order
-      constexpr int kLds = D > 1 ? (D - 1) * 24 * ((D == 8 ? kMaxBlock : kBlock) / D) : 1;
-      __shared__ T lds_acc[kLds];
+      T* lds_acc = (T*)lds_raw;
       const int per = L.sblk * L.nrhs;
       const int loc = (int)threadIdx.x - t.part * per;
       if (sel && t.part > 0) {
@@ -234,7 +242,7 @@ __device__ __forceinline__ void hop_body(const Launch& L) {
       if (L.g5out) gamma5_inplace(acc);
       v = hop_epilogue_comps<P, A, MODE, 12>(L, S, t, both, par, ne, e, 0, acc.c);
     }
-    if (L.fin != FIN_NONE) block_reduce_store(L, S, t, v);
+    if (L.fin != FIN_NONE) block_reduce_store_buf(L, S, t, v, 1, lds_red);
   }
 }
 

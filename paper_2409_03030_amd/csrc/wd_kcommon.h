@@ -208,9 +208,9 @@ __device__ void finalize_rhs(int fin, RhsState& s, double sum) {
 // parts: how many part-major groups of sblk * nrhs threads hold values (a
 // stencil whose split parts each finish a share of the output components);
 // the tree then runs over parts * sblk "sites".
-// All threads of the block must call this.
-__device__ void block_reduce_store(const Launch& L, const Slot& S, const Tile& t, double v, int parts = 1) {
-  __shared__ double lds[kMaxBlock];
+// lds: blockDim.x doubles of LDS.  All threads of the block must call this.
+__device__ void block_reduce_store_buf(const Launch& L, const Slot& S, const Tile& t, double v, int parts,
+                                       double* lds) {
   const int tid = (int)threadIdx.x;
   const int nr = L.nrhs;
   const int sb = L.sblk * parts;
@@ -236,6 +236,11 @@ __device__ void block_reduce_store(const Launch& L, const Slot& S, const Tile& t
     __syncthreads();
   }
   if (tid < nr) S.partial[(size_t)t.lblk * nr + tid] = lds[tid];
+}
+
+__device__ void block_reduce_store(const Launch& L, const Slot& S, const Tile& t, double v, int parts = 1) {
+  __shared__ double lds[kMaxBlock];
+  block_reduce_store_buf(L, S, t, v, parts, lds);
 }
 
 // Stage 2 summation order, fixed by nrhs alone so that every kernel that
@@ -286,12 +291,17 @@ __device__ void reduce_partials(const double* __restrict__ part, int npart, int 
 
 // Stage 2 in its own kernel (block b handles slot b) or in the first block of
 // the next stencil: sum the partials and run the CG scalar update.
-__device__ void gather_and_finalize(const Launch& L, const Slot& S, int fin) {
-  __shared__ double red[kRedSlots];
+// red: kRedSlots doubles of LDS.
+__device__ void gather_and_finalize_buf(const Launch& L, const Slot& S, int fin, double* red) {
   reduce_partials(S.partial, S.npart, L.nrhs, red);
   const int tid = (int)threadIdx.x;
   if (tid < L.nrhs && S.st != nullptr) finalize_rhs(fin, S.st[tid], red[tid]);
   __syncthreads();
+}
+
+__device__ void gather_and_finalize(const Launch& L, const Slot& S, int fin) {
+  __shared__ double red[kRedSlots];
+  gather_and_finalize_buf(L, S, fin, red);
 }
 
 // Stage 2 of FIN_ALPHA run by every block of the stencil that needs alpha
