@@ -572,7 +572,7 @@ def bench_cfg4(args):
     B = torch.from_numpy(qcdgen.point_sources(L)).cuda()
     lat = W.Lattice(L, BC)
     G = args.rhs_group if args.rhs_group > 0 else 4
-    for prec, recon in (("f64", 18), ("f32", 12)):
+    for prec, recon in (("f64", 18), ("f32", args.inner_recon)):
         lat.set_gauge(Ud, prec, recon)
         if args.tune_file:
             continue
@@ -625,15 +625,15 @@ def bench_cfg4(args):
     # The 12-rhs stencil against the roofline: the plain hop H_oe over all 12
     # sources (one launch of 12/G slots), event-timed inside one solve, against
     # the algorithmic bytes of 12 sources sharing one read of the links:
-    # 8 FP32-12 links (384 B) per site plus 12 x (96 B in + 96 B out), i.e.
-    # 224 B per site and source.
+    # 8 FP32-12 links (384 B; 576 B at recon 18) per site plus
+    # 12 x (96 B in + 96 B out), i.e. 224 B (240 B) per site and source.
     pt = W.SolveParams.from_buffer_copy(p)
     pt.timing = 1
     X, st = lat.solve(B, [0.1365] * 12, pt)
     s0 = st[0]
     m0 = s0["hop_inner_mode_launches"][0]
     ms0 = s0["hop_inner_mode_ms"][0] / max(1, m0)
-    ideal = half * (8 * 48 + 12 * 192)
+    ideal = half * (8 * (48 if args.inner_recon == 12 else 72) + 12 * 192)
     roof = {"bound": "hbm", "what": "FP32 plain hop H_oe over the 12 sources, event-timed in the solve (each "
                                      "launch also carries its dispatch latency; launches that skipped converged "
                                      "sources included)",
@@ -643,6 +643,7 @@ def bench_cfg4(args):
             "library_bytes_per_launch": s0["hop_inner_mode_bytes"][0] / max(1, m0),
             "note": f"{12 // G} slot(s) of {G} sources: the library's own count reads the links once per slot",
             "all_stencil_launches_gbs": s0["hop_bytes"] / (s0["hop_ms"] * 1e-3) / 1e9,
+            "links": f"f32 recon-{args.inner_recon}",
             "cache_resident": "the 16^3x32 FP32 link field (25 MB) and the 12-source vectors (about 190 MB) fit "
                               "in the 256 MB Infinity Cache"}
     return _common_out(args, flops / tot_batched / 1e9, "GFLOP/s", tot_batched / 3 * 1e3, "f32",
@@ -1084,6 +1085,7 @@ def main():
     ap.add_argument("--rate", type=float, default=50.0, help="cfg5: Poisson arrival rate per second")
     ap.add_argument("--lattice", default="24,24,24,48", help="stencil: lattice extents x,y,z,t")
     ap.add_argument("--rhs-group", type=int, default=0, help="cfg4: sources per slot (0: library default)")
+    ap.add_argument("--inner-recon", type=int, default=12, choices=(12, 18), help="cfg4: FP32 link recon")
     ap.add_argument("--save-tune", default=None, help="write the tuning table to this file")
     ap.add_argument("--tune-file", default=None, help="load this tuning table instead of autotuning")
     ap.add_argument("--stag-shape", default=None,
