@@ -191,7 +191,8 @@ void wd_solve_params_default(wd_solve_params* params);
  * updates (x_h += x_l, r_h = b - A x_h recomputed with the FP64 store, FP64
  * norms).  Needs the FP64 gauge store, and the inner precision's store when
  * inner != F64.  stats has nrhs entries (host).  Blocks the host.  Returns
- * WD_OK when every rhs converged, else the first failing rhs status. */
+ * WD_OK when every rhs converged, else the first failing rhs status.  Many
+ * rhs may run as consecutive waves (wd_solve_batch). */
 wd_status wd_solve_DdagD(wd_lattice lat, void* x, const void* b, int32_t nrhs, const double* kappa,
                          const wd_solve_params* params, void* ws, size_t ws_bytes,
                          wd_solve_stats* stats, void* stream);
@@ -357,7 +358,11 @@ size_t wd_batch_workspace_bytes(int32_t nreq, const wd_solve_request* reqs, cons
 
 /* Solve every request with one stencil launch per CG phase covering all of
  * them (uneven lattices in one grid).  stats holds sum(nrhs) entries, in
- * request order.  Blocks the host. */
+ * request order.  Blocks the host.  A single request whose rhs groups'
+ * inner-loop vectors (the inner- and accumulation-precision vectors) exceed
+ * 384 MB runs as consecutive waves of groups within that budget when a wave
+ * holds at least two groups (each wave's results are those of its rhs solved
+ * alone; its stats report that wave's time). */
 wd_status wd_solve_batch(int32_t nreq, const wd_solve_request* reqs, const wd_solve_params* params,
                          void* ws, size_t ws_bytes, wd_solve_stats* stats, void* stream);
 

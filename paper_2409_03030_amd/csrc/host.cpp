@@ -383,6 +383,29 @@ Tune pick_shape(const std::vector<std::pair<Tune, double>>& timed_all, long long
   return bt;
 }
 
+// First item of each wave (kWaveBytes): one wave unless a single request's
+// groups exceed the budget and at least two of its largest groups fit in it.
+static std::vector<size_t> wave_starts(const std::vector<EItem>& items, int32_t nreq) {
+  std::vector<size_t> w{0};
+  if (nreq != 1 || items.size() < 2) return w;
+  auto inner = [](const EItem& it) { return it.lay.total - it.lay.off_x; };
+  size_t tot = 0, big = 0;
+  for (const EItem& it : items) {
+    tot += inner(it);
+    big = std::max(big, inner(it));
+  }
+  if (tot <= kWaveBytes || 2 * big > kWaveBytes) return w;
+  size_t acc = 0;
+  for (size_t k = 0; k < items.size(); ++k) {
+    if (acc > 0 && acc + inner(items[k]) > kWaveBytes) {
+      w.push_back(k);
+      acc = 0;
+    }
+    acc += inner(items[k]);
+  }
+  return w;
+}
+
 }  // namespace wd
 
 using namespace wd;
@@ -684,7 +707,22 @@ wd_status wd_solve_batch(int32_t nreq, const wd_solve_request* reqs, const wd_so
     it.state_index = si;
     si += it.nrhs;
   }
-  return run_batch(items, *params, states, (hipStream_t)stream, stats);
+  const std::vector<size_t> waves = wave_starts(items, nreq);
+  if (waves.size() == 1) return run_batch(items, *params, states, (hipStream_t)stream, stats);
+  // consecutive waves: each solves its groups to the end (states and stats of
+  // a wave are the contiguous entries of its rhs)
+  wd_status worst = WD_OK;
+  for (size_t k = 0; k < waves.size(); ++k) {
+    const size_t a = waves[k], e = k + 1 < waves.size() ? waves[k + 1] : items.size();
+    std::vector<EItem> sub(items.begin() + (long)a, items.begin() + (long)e);
+    const int s0 = items[a].state_index;
+    const wd_status r = run_batch(sub, *params, states + s0, (hipStream_t)stream, stats + s0);
+    if (r != WD_OK && r != WD_ENOTCONVERGED && r != WD_ENONFINITE) return r;
+    if (worst == WD_OK) worst = r;
+  }
+  if (worst == WD_ENONFINITE) set_error("non-finite value met in the solve");
+  if (worst == WD_ENOTCONVERGED) set_error("solve did not reach the tolerance within maxiter");
+  return worst;
 }
 
 wd_status wd_solve_DdagD(wd_lattice lat, void* x, const void* b, int32_t nrhs, const double* kappa,

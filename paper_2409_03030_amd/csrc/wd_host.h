@@ -59,6 +59,14 @@ bool valid_tune(const Tune& t, int nrhs, int prec);
 constexpr int kFoldPartials = 1024;
 constexpr long long kFoldReads = 1LL << 19;
 
+// Cache blocking of a single request's rhs groups: when the vectors that
+// every CG iteration touches (the inner- and accumulation-precision vectors
+// of all groups) exceed kWaveBytes, the groups run as consecutive waves of
+// at most kWaveBytes each, provided a wave still holds two groups or more
+// (the groups of one launch share the links' reads).  1.5 x the Infinity
+// Cache: a 12-source FP32-inner request at 16^3x32 (378 MB) stays one wave.
+constexpr size_t kWaveBytes = (size_t)384 << 20;
+
 // The autotuners' choice among timed stencil shapes (ms per launch) for a
 // lattice of n sites per parity: each shape is costed as per_iter of its
 // launches plus a finalize kernel (about 5 us) for each of the two CG

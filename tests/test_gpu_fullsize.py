@@ -182,6 +182,9 @@ def test_cfg4_twelve_point_sources(cfg4, kappa):
 
 
 def test_cfg4_thirty_six_sources_mixed_kappa(cfg4):
+    """36 sources in one request: their FP32-inner vectors (1.1 GB) exceed the
+    cache-blocking budget, so the request runs as waves of 12 sources, each
+    bitwise the same as that 12-source request solved alone."""
     L, U, B, lat = cfg4
     W = _W()
     p = W.default_params(inner="f32", delta=1e-2)
@@ -195,6 +198,10 @@ def test_cfg4_thirty_six_sources_mixed_kappa(cfg4):
     # iterations grow with kappa (the operator's condition number does)
     its = [st[12 * k]["iters"] for k in range(3)]
     assert its[0] < its[1] < its[2], its
+    for k in range(3):
+        Xk, stk = lat.solve(_dev(B), ks[12 * k: 12 * k + 12], p)
+        assert np.array_equal(_host(Xk), X[12 * k: 12 * k + 12]), k
+        assert [s["iters"] for s in stk] == [s["iters"] for s in st[12 * k: 12 * k + 12]], k
 
 
 @pytest.mark.parametrize("inner", ["f16", "f64"])
