@@ -423,15 +423,17 @@ int BlockPlanner::next(const RhsState* hs, size_t n, int inflight, const int* id
 
 int Engine::reliable_every() const { return 0; }
 
-// K inner iterations, then one reliable-update sequence: held rhs (converged
-// iterate, delta drop, or maxiter) get their FP64 true residual there.  The
-// host sizes K so that a block ends where the next such event is expected.
-wd_status Engine::enqueue_direct(int K) {
+// K inner iterations, then (ru) one reliable-update sequence: held rhs
+// (converged iterate, delta drop, or maxiter) get their FP64 true residual
+// there.  The host sizes K so that a block ends where the next such event is
+// expected, and leaves the sequence out of a block not expected to reach one
+// (it would run masked).
+wd_status Engine::enqueue_direct(int K, bool ru) {
   for (int j = 0; j < K; ++j) {
     wd_status s = run_iteration();
     if (s != WD_OK) return s;
   }
-  return run_reliable();
+  return ru ? run_reliable() : WD_OK;
 }
 
 // Instantiated graphs, shared by every engine of the process and keyed by the
@@ -449,9 +451,9 @@ std::vector<GraphEntry> g_graphs;  // most recently used last
 constexpr size_t kGraphCap = 48;
 }  // namespace
 
-// A block is K copies of one iteration's launches plus one reliable-update
-// sequence, so its key is the hash of those launches and K.
-uint64_t Engine::block_key(int K) {
+// A block is K copies of one iteration's launches plus, or not, one
+// reliable-update sequence, so its key is the hash of those launches, K and ru.
+uint64_t Engine::block_key(int K, bool ru) {
   if (base_key_ == 0) {
     uint64_t h = 1469598103934665603ull;
     hash_ = &h;
@@ -460,17 +462,18 @@ uint64_t Engine::block_key(int K) {
     hash_ = nullptr;
     base_key_ = h | 1;
   }
-  return fnv1a(base_key_, &K, sizeof K);
+  const int kr[2] = {K, ru ? 1 : 0};
+  return fnv1a(base_key_, kr, sizeof kr);
 }
 
-wd_status Engine::enqueue_block(int K) {
+wd_status Engine::enqueue_block(int K, bool ru) {
   if (items.empty()) return WD_OK;
-  const int ru = reliable_every();
+  const int every = reliable_every();
   if (K < 1) K = 1;
-  if (ru > 0 && K % ru) K = (K / ru + 1) * ru;
+  if (every > 0 && K % every) K = (K / every + 1) * every;
   ++blocks;
-  if (!p_.use_graph || timer_) return enqueue_direct(K);
-  const uint64_t key = block_key(K);
+  if (!p_.use_graph || timer_) return enqueue_direct(K, ru);
+  const uint64_t key = block_key(K, ru);
   std::lock_guard<std::mutex> lk(g_graph_mu);
   GraphEntry ent{0, nullptr, nullptr};
   for (size_t i = 0; i < g_graphs.size(); ++i)
@@ -488,10 +491,10 @@ wd_status Engine::enqueue_block(int K) {
     if (!seen) {
       if (seen_.size() >= 256) seen_.erase(seen_.begin());
       seen_.push_back(key);
-      return enqueue_direct(K);
+      return enqueue_direct(K, ru);
     }
     WD_HIP(hipStreamBeginCapture(stream_, hipStreamCaptureModeThreadLocal));
-    wd_status s = enqueue_direct(K);
+    wd_status s = enqueue_direct(K, ru);
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamEndCapture(stream_, &g);
     if (s != WD_OK) {
@@ -599,8 +602,8 @@ wd_status run_batch(std::vector<EItem>& items, const wd_solve_params& p, RhsStat
     };
     std::vector<Posted> fly;
     int next_buf = 0;
-    auto post = [&](int K) -> wd_status {
-      wd_status s = eng.enqueue_block(K);
+    auto post = [&](int K, bool ru) -> wd_status {
+      wd_status s = eng.enqueue_block(K, ru);
       if (s != WD_OK) return s;
       const int k = next_buf;
       next_buf ^= 1;
@@ -612,8 +615,8 @@ wd_status run_batch(std::vector<EItem>& items, const wd_solve_params& p, RhsStat
       return WD_OK;
     };
     const int k0 = std::min(plan.kmax, 8);
-    if ((result = post(k0)) != WD_OK) break;
-    if ((result = post(k0)) != WD_OK) break;
+    if ((result = post(k0, true)) != WD_OK) break;
+    if ((result = post(k0, true)) != WD_OK) break;
     long long iters_posted = 2LL * k0;
     for (;;) {
       const Posted done = fly.front();
@@ -629,14 +632,16 @@ wd_status run_batch(std::vector<EItem>& items, const wd_solve_params& p, RhsStat
       if (K == 0) break;  // every rhs finished
       if (iters_posted > (long long)p.maxiter + 64LL * plan.kmax) break;  // device caps iterations; bounds the host loop
       if (K < 0) {
-        if (fly.empty() && (result = post(1)) != WD_OK) break;
+        if (fly.empty() && (result = post(1, true)) != WD_OK) break;
         continue;
       }
-      if ((result = post(K)) != WD_OK) break;
+      // the reliable-update sequence only in a block expected to reach the
+      // next event (a held rhs otherwise waits for the next block's)
+      if ((result = post(K, K + 0.5 >= plan.left)) != WD_OK) break;
       iters_posted += K;
       if (fly.size() < 2 && K >= plan.kmax && (plan.nrun > 1 || plan.left >= 2.0 * K)) {
         // far from any event: keep a second block queued so the GPU never waits
-        if ((result = post(K)) != WD_OK) break;
+        if ((result = post(K, 2 * K + 0.5 >= plan.left)) != WD_OK) break;
         iters_posted += K;
       }
     }

@@ -163,7 +163,7 @@ class Engine {
   wd_status start_item(EItem* it);    // enqueue state init, source import, INIT
   // Enqueue K inner iterations (K a multiple of reliable_every()), with a
   // reliable-update sequence after every reliable_every() iterations.
-  wd_status enqueue_block(int K);
+  wd_status enqueue_block(int K, bool ru = true);
   wd_status export_item(EItem* it);   // x = x_h (boundary layout)
   void set_changed() { base_key_ = 0; }
   int max_block() const;              // block size for a cold start
@@ -175,8 +175,8 @@ class Engine {
   wd_status run_phase(const std::vector<EItem*>& list, const Phase& ph);
   wd_status run_iteration();
   wd_status run_reliable();
-  wd_status enqueue_direct(int K);
-  uint64_t block_key(int K);
+  wd_status enqueue_direct(int K, bool ru);
+  uint64_t block_key(int K, bool ru);
   wd_solve_params p_;
   bool eo_;
   int op_;
