@@ -600,9 +600,9 @@ WD_HD void hop_dir(const Geom& g, const Coord& k, int parity, int s, int rhs, in
 // products of half pairs with FP32 accumulation (v_dot2_f32_f16; the half
 // products are exact in FP32), and the neighbour's scale, with the boundary
 // sign, multiplies the FP32 product as it is accumulated (one FMA per real).
-// Links are used as stored; the third row of a 12-real link is rebuilt in
-// FP32 and rounded to halves like the stored rows.  A complex is a pair of
-// halves (re, im):
+// Links are used as stored; the third row of a 12-real link is rebuilt from
+// half dot products accumulated in FP32 and rounded to halves like the
+// stored rows.  A complex is a pair of halves (re, im):
 //   Re(U h) = sum dot2((U.re, -U.im), h)       Im(U h) = sum dot2(U, (h.im, h.re))
 //   Re(U^dag h) = sum dot2(U, h)               Im(U^dag h) = sum dot2((U.re, -U.im), (h.im, h.re))
 // ---------------------------------------------------------------------------
@@ -660,16 +660,31 @@ __device__ __forceinline__ void hop_finish16(HopBuf16& b, bool g5in, spinor<floa
   constexpr int MU = H >> 1;
   constexpr int DIR = (H & 1) ? -1 : 1;
   wd_h2 uc[9];  // (U.re, -U.im)
+#pragma unroll
+  for (int q = 0; q < 6; ++q) uc[q] = h2_conj(b.u[q]);
   if constexpr (R == 12) {
-    su3<float> f;
+    // Third row = conj(row0 x row1), from half dot products accumulated in
+    // FP32 (the products of halves are exact there), rounded to halves like
+    // the stored rows.  For e = conj(a d - b' c) with b' the negated row-0
+    // entry:  Re e = dot(a, (d.re, -d.im)) + dot(b', (c.re, -c.im)),
+    //         Im e = dot(a, (-d.im, -d.re)) + dot(b', (-c.im, -c.re)).
+    wd_h2 ng[3], sw[3];  // -row0 entries; (-x.im, -x.re) of the row-1 entries
 #pragma unroll
-    for (int q = 0; q < 6; ++q) f.e[q] = {(float)b.u[q].x, (float)b.u[q].y};
-    reconstruct_row2(f);
+    for (int q = 0; q < 3; ++q) {
+      ng[q] = -b.u[q];
+      sw[q] = -h2_swap(b.u[3 + q]);
+    }
+    // (a, b', d, c) row indices: e6 = conj(u1 u5 - u2 u4), e7 = conj(u2 u3 - u0 u5), e8 = conj(u0 u4 - u1 u3)
+    constexpr int A_[3] = {1, 2, 0}, B_[3] = {2, 0, 1}, D_[3] = {5, 3, 4}, C_[3] = {4, 5, 3};
 #pragma unroll
-    for (int q = 6; q < 9; ++q) b.u[q] = (wd_h2){(_Float16)f.e[q].re, (_Float16)f.e[q].im};
+    for (int q = 0; q < 3; ++q) {
+      const float re = dot2h(b.u[A_[q]], uc[D_[q]], dot2h(ng[B_[q]], uc[C_[q]], 0.f));
+      const float im = dot2h(b.u[A_[q]], sw[D_[q] - 3], dot2h(ng[B_[q]], sw[C_[q] - 3], 0.f));
+      b.u[6 + q] = (wd_h2){(_Float16)re, (_Float16)im};
+    }
   }
 #pragma unroll
-  for (int q = 0; q < 9; ++q) uc[q] = h2_conj(b.u[q]);
+  for (int q = 6; q < 9; ++q) uc[q] = h2_conj(b.u[q]);
   if (g5in) {
 #pragma unroll
     for (int q = 6; q < 12; ++q) b.s[q] = -b.s[q];
