@@ -376,6 +376,10 @@ def solve_workload(args, name, W, torch, tuned):
             "rel_diff_vs_plain_fp64_x": (torch.linalg.vector_norm(xm - x) / torch.linalg.vector_norm(x)).item(),
             "stencil_gbs": rm["achieved_gbs"],
             "stencil_ms_avg": rm["hop_ms_avg"],
+            "stencil_note": "all stencil launches of the event-timed solve (inner precision and the FP64 "
+                            "reliable updates): algorithmic bytes over summed durations; the inner link field "
+                            "(FP32-12 127 MB, FP16-12 64 MB) and inner vectors partly stay in the Infinity Cache, "
+                            "so this is not an HBM figure",
             "dw_gflops": dw_flops(sm, half) / dtm / 1e9,
             "speedup_vs_plain_fp64": dt / dtm,
         }
