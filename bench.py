@@ -378,8 +378,8 @@ def solve_workload(args, name, W, torch, tuned):
             "stencil_ms_avg": rm["hop_ms_avg"],
             "stencil_note": "all stencil launches of the event-timed solve (inner precision and the FP64 "
                             "reliable updates): algorithmic bytes over summed durations; the inner link field "
-                            "(FP32-12 127 MB, FP16-12 64 MB) and inner vectors partly stay in the Infinity Cache, "
-                            "so this is not an HBM figure",
+                            "and vectors (at 24^3x48 FP32-12 links 127 MB, FP16-12 64 MB) partly stay in the "
+                            "Infinity Cache, so this is not an HBM figure",
             "dw_gflops": dw_flops(sm, half) / dtm / 1e9,
             "speedup_vs_plain_fp64": dt / dtm,
         }
