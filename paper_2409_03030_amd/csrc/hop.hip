@@ -1,10 +1,11 @@
 // The Wilson hopping stencil with fused epilogues.
 //
-// One thread computes (H in)(x) for one output site x and one rhs: for each
-// of the 8 directions it loads the neighbour spinor, spin-projects it to a
-// half spinor (adds and i-swaps only), multiplies the half spinor by the
-// link (U or U^dag), applies the boundary sign, and accumulates the rebuilt
-// full spinor: 8 x (12 + 132) + 7 x 24 = 1320 flop per output site.
+// One thread computes (H in)(x) for one output site x and one rhs (or a
+// share of its 8 hops, when `split` threads take one site): for each
+// direction it loads the neighbour spinor, spin-projects it to a half spinor
+// (adds and i-swaps only), multiplies the half spinor by the link (U or
+// U^dag), applies the boundary sign, and accumulates the rebuilt full
+// spinor: 8 x (12 + 132) + 7 x 24 = 1320 flop per output site.
 // The epilogue then forms one of
 //   HOP_PLAIN : out = [g5] H [g5] in
 //   HOP_XPAY  : out = aux - c [g5] H [g5] in          (+ ||out||^2, FIN_ALPHA)
