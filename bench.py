@@ -200,6 +200,7 @@ def instrumented(lat, bd, kappa, params):
         "dominant_mode": dom,
         "hop_ms_total": s["hop_ms"],
         "hop_launches": s["hop_launches"],
+        "skipped_launches": s["hop_skipped"],
         "hop_ms_avg": s["hop_ms"] / max(1, s["hop_launches"]),
         "bytes_per_launch": s["hop_bytes"] / max(1, s["hop_launches"]),
         "achieved_gbs": gbs,
@@ -412,8 +413,10 @@ def solve_workload(args, name, W, torch, tuned):
         "bytes_per_site": dom_bytes / half,
         "output_sites_per_launch": half,
         "in_solve": {"by_mode": roof["modes"],
+                     "skipped_launches": roof["skipped_launches"],
                      "note": "hipEvents around each launch of one plain FP64 solve (event-to-event, so "
-                             "each launch also carries its dispatch latency)"},
+                             "each launch also carries its dispatch latency); launches whose slots all "
+                             "skipped their work (flagged by the kernels) are left out"},
         "cg_residual_stencil": {
             "kernel": cgr_name, "avg_launch_ms": cgr_ms, "bytes_per_launch": cgr_bytes,
             "achieved": cgr_bytes / (cgr_ms * 1e-3) / 1e9,
@@ -639,8 +642,9 @@ def bench_cfg4(args):
     ms0 = s0["hop_inner_mode_ms"][0] / max(1, m0)
     ideal = half * (8 * (48 if args.inner_recon == 12 else 72) + 12 * 192)
     roof = {"bound": "hbm", "what": "FP32 plain hop H_oe over the 12 sources, event-timed in the solve (each "
-                                     "launch also carries its dispatch latency; launches that skipped converged "
-                                     "sources included)",
+                                     "launch also carries its dispatch latency; launches whose slots all skipped "
+                                     "their work left out, launches that skipped some converged sources counted "
+                                     "with every source's bytes)",
             "avg_launch_ms": ms0, "bytes_per_launch_12rhs_links_once": ideal, "bytes_per_site_rhs": ideal / half / 12,
             "achieved": ideal / (ms0 * 1e-3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": ideal / (ms0 * 1e-3) / 1e9 / HBM_PEAK_GBS,

@@ -99,12 +99,17 @@ typedef struct {
   int32_t status;            /* WD_OK, WD_ENOTCONVERGED or WD_ENONFINITE for this rhs */
   int32_t iters;             /* inner CG iterations */
   int32_t reliable_updates;  /* FP64 true-residual recomputations */
-  int32_t pad;
+  int32_t hop_skipped;       /* with timing=1: stencil launches left out of the hop_* figures below
+                                because every slot skipped its work (masked after convergence, or a
+                                reliable-update sequence with nothing held), as the kernels flag it in
+                                a ring of 65536 flags per device (a 256 KiB device array of the library;
+                                timed solves running on one GPU at once share it, and their counts are
+                                then unreliable; launches beyond the ring are counted as working) */
   double true_resid;         /* last FP64 true relative residual */
   double iter_resid;         /* last iterated relative residual */
   double seconds;            /* wall time of the whole solve call */
-  double hop_ms;             /* with timing=1: summed duration of the stencil launches */
-  int64_t hop_launches;      /* with timing=1: number of stencil launches timed */
+  double hop_ms;             /* with timing=1: summed duration of the stencil launches that worked */
+  int64_t hop_launches;      /* with timing=1: number of those launches */
   int64_t hop_site_updates;  /* stencil output sites x rhs processed by those launches */
   double hop_bytes;          /* algorithmic bytes of those launches: each launch reads its 8 links per
                                 output site once (shared by the rhs), its input spinor once per site and

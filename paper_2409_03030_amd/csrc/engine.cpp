@@ -221,6 +221,7 @@ wd_status Engine::run_phase(const std::vector<EItem*>& list, const Phase& ph0) {
       continue;
     }
     if (ph.hop) {
+      L.work_flag = timer_ ? timer_->next_flag() : nullptr;
       hipError_t e = timer_ ? timer_->begin(stream_) : hipSuccess;
       if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
       e = op_ == OP_STAG ? launch_stag(L, ph.prec, recon, ph.mode, stream_)
@@ -535,7 +536,8 @@ wd_status stats_from_state(const RhsState& s, double seconds, const HopTimer* t,
   o.iter_resid = std::sqrt(s.iter_res2 / bn);
   o.seconds = seconds;
   if (t && t->on) {
-    o.hop_launches = (long long)(t->used / 2);
+    o.hop_launches = (long long)(t->dur.size()) - t->nskipped;
+    o.hop_skipped = (int32_t)t->nskipped;
     o.hop_site_updates = t->site_updates;
     o.hop_bytes = t->bytes;
   }
@@ -565,6 +567,28 @@ static hipStream_t solve_stream(hipStream_t s, wd_status* st) {
   return own;
 }
 
+// The work flags of timed stencil launches (HopTimer): a ring per device,
+// shared by the timed solves running on it at the same time (their skipped
+// counts are then unreliable).  Its address is looked up once per device.
+static __device__ int timing_flags[kTimingFlags];
+static std::mutex g_flags_mu;
+static int* g_flags_ptr[64];
+
+static wd_status timing_flags_address(int** out) {
+  int dev = -1;
+  WD_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= 64) return fail(WD_EDEVICE, "device %d out of range", dev);
+  std::lock_guard<std::mutex> lk(g_flags_mu);
+  if (!g_flags_ptr[dev]) {
+    void* q = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&q, HIP_SYMBOL(timing_flags));
+    if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(timing_flags)");
+    g_flags_ptr[dev] = (int*)q;
+  }
+  *out = g_flags_ptr[dev];
+  return WD_OK;
+}
+
 wd_status run_batch(std::vector<EItem>& items, const wd_solve_params& p, RhsState* states, hipStream_t stream_in,
                     wd_solve_stats* stats, int op) {
   auto t0 = std::chrono::steady_clock::now();
@@ -573,6 +597,12 @@ wd_status run_batch(std::vector<EItem>& items, const wd_solve_params& p, RhsStat
   if (sst != WD_OK) return sst;
   HopTimer timer;
   timer.on = p.timing != 0;
+  if (timer.on) {
+    wd_status fs = timing_flags_address(&timer.flags);
+    if (fs != WD_OK) return fs;
+    const hipError_t e = hipMemsetAsync(timer.flags, 0, kTimingFlags * sizeof(int), stream);
+    if (e != hipSuccess) return hip_fail(e, "timing flags clear");
+  }
   Engine eng(p, stream, states, timer.on ? &timer : nullptr, op);
   size_t nst = 0;
   for (auto& it : items) nst += (size_t)it.nrhs;
@@ -667,6 +697,13 @@ wd_status run_batch(std::vector<EItem>& items, const wd_solve_params& p, RhsStat
   if (result != WD_OK) {
     timer.release();
     return result;
+  }
+  if (timer.on) {
+    const hipError_t e = timer.classify();
+    if (e != hipSuccess) {
+      timer.release();
+      return hip_fail(e, "timing flags copy");
+    }
   }
   const double hop_ms = timer.on ? timer.total_ms() : 0.0;
   double mms[4], mb[4], ims[4], ib[4];

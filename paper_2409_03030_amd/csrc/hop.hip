@@ -142,6 +142,7 @@ __device__ __forceinline__ void hop_body(const Launch& L) {
   // held ones), and the mask of a reducing launch reads states that no block
   // of it changes.  Masked iterations after convergence then cost a launch.
   if (!slot_selected(L, S)) return;
+  if (L.work_flag != nullptr && t.lblk == 0 && threadIdx.x == 0) *L.work_flag = 1;
   const bool both = L.parity == 2;
   const int par = t.parity;
   const size_t ne = (size_t)S.g.n * L.nrhs;

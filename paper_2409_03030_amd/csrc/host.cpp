@@ -209,11 +209,41 @@ hipError_t HopTimer::end(hipStream_t s, long long sites, double b, int m) {
   if (!on) return hipSuccess;
   hipError_t r = hipEventRecord(ev[used + 1], s);
   used += 2;
-  site_updates += sites;
-  bytes += b;
   mode.push_back(m);
   mode_bytes.push_back(b);
+  mode_sites.push_back(sites);
   return r;
+}
+
+hipError_t HopTimer::classify() {
+  const size_t nl = std::min(used / 2, mode.size());
+  dur.assign(nl, -1.f);
+  skipped.assign(nl, 0);
+  for (size_t i = 0; i < nl; ++i) {
+    float t = 0.f;
+    if (hipEventElapsedTime(&t, ev[2 * i], ev[2 * i + 1]) == hipSuccess) dur[i] = t;
+  }
+  if (flags) {
+    std::vector<int> f(std::min(nl, (size_t)kTimingFlags));
+    if (!f.empty()) {
+      const hipError_t e = hipMemcpy(f.data(), flags, f.size() * sizeof(int), hipMemcpyDeviceToHost);
+      if (e != hipSuccess) return e;
+    }
+    for (size_t i = 0; i < f.size(); ++i) skipped[i] = f[i] == 0;
+  }
+  site_updates = 0;
+  bytes = 0.0;
+  nskipped = 0;
+  for (size_t i = 0; i < nl; ++i) {
+    if (dur[i] < 0.f) continue;
+    if (skipped[i]) {
+      ++nskipped;
+      continue;
+    }
+    site_updates += mode_sites[i];
+    bytes += mode_bytes[i];
+  }
+  return hipSuccess;
 }
 
 void HopTimer::by_mode(double ms[4], long long n[4], double b[4], int prec) {
@@ -222,14 +252,13 @@ void HopTimer::by_mode(double ms[4], long long n[4], double b[4], int prec) {
     n[m] = 0;
     b[m] = 0.0;
   }
-  for (size_t i = 0; i + 1 < used && i / 2 < mode.size(); i += 2) {
-    float t = 0.f;
-    if (hipEventElapsedTime(&t, ev[i], ev[i + 1]) != hipSuccess) continue;
-    const int m = mode[i / 2] & 3;
-    if (prec >= 0 && (mode[i / 2] >> 2) != prec) continue;
-    ms[m] += t;
+  for (size_t i = 0; i < dur.size(); ++i) {
+    if (dur[i] < 0.f || skipped[i]) continue;
+    const int m = mode[i] & 3;
+    if (prec >= 0 && (mode[i] >> 2) != prec) continue;
+    ms[m] += dur[i];
     n[m] += 1;
-    b[m] += mode_bytes[i / 2];
+    b[m] += mode_bytes[i];
   }
 }
 
@@ -264,10 +293,8 @@ double stag_launch_bytes(int prec, int recon, int mode, long long sites, int nrh
 
 double HopTimer::total_ms() {
   double t = 0.0;
-  for (size_t i = 0; i + 1 < used; i += 2) {
-    float ms = 0.f;
-    if (hipEventElapsedTime(&ms, ev[i], ev[i + 1]) == hipSuccess) t += ms;
-  }
+  for (size_t i = 0; i < dur.size(); ++i)
+    if (dur[i] >= 0.f && !skipped[i]) t += dur[i];
   return t;
 }
 
@@ -276,6 +303,9 @@ void HopTimer::release() {
   ev.clear();
   mode.clear();
   mode_bytes.clear();
+  mode_sites.clear();
+  dur.clear();
+  skipped.clear();
   used = 0;
 }
 

@@ -30,6 +30,7 @@ __device__ __forceinline__ void stag_body(const Launch& L) {
   // Launches with a reduction run every block: every block partial of the
   // slot must be written for the finalize step.
   if (L.fin == FIN_NONE && !slot_selected(L, S)) return;
+  if (L.work_flag != nullptr && t.lblk == 0 && threadIdx.x == 0 && slot_selected(L, S)) *L.work_flag = 1;
   const bool both = L.parity == 2;
   const int par = t.parity;
   const size_t ne = (size_t)S.g.n * L.nrhs;

@@ -92,16 +92,31 @@ Launch base_launch(int nrhs, const Tune& t, int parity);
 int min_sblk(int nrhs);  // smallest block size the partial buffers allow
 
 // Events around stencil launches (timing mode).
+// Event timing of every stencil launch of a solve (timing = 1).  A launch
+// whose slots all skip their work (masked after convergence, or a reliable-
+// update sequence with nothing held) returns at once: the kernels set the
+// launch's work flag (Launch::work_flag, one int per timed launch in a ring
+// of kTimingFlags per device) only when a slot did its work, and the figures
+// below leave the other launches out, so that their algorithmic bytes are not
+// counted against a few microseconds.  Launches beyond the ring are counted.
+constexpr int kTimingFlags = 1 << 16;
 struct HopTimer {
   bool on = false;
   std::vector<hipEvent_t> ev;
   size_t used = 0;
-  long long site_updates = 0;
+  int* flags = nullptr;              // device ring of kTimingFlags work flags, zeroed at the start
+  std::vector<int> mode;             // epilogue mode + 4 x precision of each timed launch
+  std::vector<double> mode_bytes;    // its algorithmic bytes
+  std::vector<long long> mode_sites;  // its output sites x rhs
+  std::vector<float> dur;            // after classify(): ms of each launch
+  std::vector<char> skipped;         // after classify(): 1 if it skipped its work
+  long long site_updates = 0;        // after classify(): over the launches that worked
   double bytes = 0.0;
-  std::vector<int> mode;          // epilogue mode + 4 x precision of each timed launch
-  std::vector<double> mode_bytes;  // its algorithmic bytes
+  long long nskipped = 0;
+  int* next_flag() const { return flags && used / 2 < (size_t)kTimingFlags ? flags + used / 2 : nullptr; }
   hipError_t begin(hipStream_t s);
   hipError_t end(hipStream_t s, long long sites, double bytes, int mode);
+  hipError_t classify();  // after the stream has finished
   double total_ms();
   // per epilogue mode; prec >= 0: only the launches at that precision
   void by_mode(double ms[4], long long n[4], double b[4], int prec = -1);

@@ -88,6 +88,7 @@ struct Launch {
                         // block count); logical block b is block b / nslots of slot b % nslots, so the
                         // groups' blocks for the same sites run next to each other (links read from the L2)
   int total_blocks;
+  int* work_flag;       // timed launches: set to 1 by a block of a slot that does its work; else null
   double coef;          // epilogue coefficient when no RhsState is attached
   double coef2;         // second coefficient (staggered XPAY) when no RhsState is attached
 };

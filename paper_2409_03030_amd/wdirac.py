@@ -54,7 +54,7 @@ class SolveStats(C.Structure):
         ("status", C.c_int32),
         ("iters", C.c_int32),
         ("reliable_updates", C.c_int32),
-        ("pad", C.c_int32),
+        ("hop_skipped", C.c_int32),
         ("true_resid", C.c_double),
         ("iter_resid", C.c_double),
         ("seconds", C.c_double),
@@ -73,8 +73,6 @@ class SolveStats(C.Structure):
     def as_dict(self):
         d = {}
         for k, _ in self._fields_:
-            if k == "pad":
-                continue
             v = getattr(self, k)
             d[k] = list(v) if hasattr(v, "__len__") else v
         return d

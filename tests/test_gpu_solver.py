@@ -345,3 +345,45 @@ def test_batch_mixes_link_recons(inner):
         xa, sa = lat.solve(_dev(b), k, p)
         assert np.array_equal(x, _host(xa))
         assert st[0]["iters"] == sa[0]["iters"]
+
+
+@pytest.mark.parametrize("inner", ["f64", "f16"])
+def test_timed_solve_stats(inner):
+    """A solve with per-launch timing returns bitwise the solution of the untimed
+    solve, and its stencil figures are consistent: the per-mode launches add up
+    to the launches counted, every counted launch carries its mode's algorithmic
+    bytes (8 links, input spinor, epilogue vectors per output site), and the
+    launches left out as skipped are few beside them."""
+    L = (8, 8, 8, 16)
+    g = qcdgen.rng(177)
+    U = qcdgen.links_exp(L, 0.3, g)
+    b = qcdgen.gaussian_spinor(L, g)
+    W = _W()
+    lat = _lattice(L, U, [("f64", 12), ("f16", 12)])
+    p = W.default_params(inner=inner, delta=1e-2 if inner != "f64" else 0.0)
+    x0, st0 = lat.solve(_dev(b), 0.1365, p)
+    pt = W.SolveParams.from_buffer_copy(p)
+    pt.timing = 1
+    x1, st1 = lat.solve(_dev(b), 0.1365, pt)
+    assert np.array_equal(_host(x0), _host(x1))
+    s = st1[0]
+    assert s["status"] == 0 and s["iters"] == st0[0]["iters"]
+    assert sum(s["hop_mode_launches"]) == s["hop_launches"] > 0
+    assert 0 <= s["hop_skipped"] <= s["hop_launches"]
+    half = L[0] * L[1] * L[2] * L[3] // 2
+    link = {"f64": 96, "f16": 24}
+    sp = {"f64": 192, "f16": 52}
+    acc = {"f64": 192, "f16": 96}
+    for m in range(4):
+        n = s["hop_mode_launches"][m]
+        if n == 0:
+            continue
+        per = s["hop_mode_bytes"][m] / n
+        # inner-precision launches and FP64 reliable-update launches mix in
+        # a mixed solve: their bytes per launch lie between the two formats'
+        lo = min(8 * link[q] + sp[q] + (sp[q], 2 * sp[q], sp[q] + 2 * acc[q], sp[q] + 2 * 192)[m]
+                 for q in {inner, "f64"}) * half
+        hi = max(8 * link[q] + sp[q] + (sp[q], 2 * sp[q], sp[q] + 2 * acc[q], sp[q] + 2 * 192)[m]
+                 for q in {inner, "f64"}) * half
+        assert lo - 1 <= per <= hi + 1, (m, per, lo, hi)
+        assert s["hop_mode_ms"][m] > 0.0
