@@ -652,8 +652,8 @@ def bench_cfg4(args):
             "note": f"{12 // G} slot(s) of {G} sources: the library's own count reads the links once per slot",
             "all_stencil_launches_gbs": s0["hop_bytes"] / (s0["hop_ms"] * 1e-3) / 1e9,
             "links": f"f32 recon-{args.inner_recon}",
-            "cache_resident": "the 16^3x32 FP32 link field (25 MB) and the 12-source vectors (about 190 MB) fit "
-                              "in the 256 MB Infinity Cache"}
+            "cache_resident": "the 16^3x32 FP32 link field (25 MB) fits in the 256 MB Infinity Cache, the 12 "
+                              "sources' inner-loop vectors (378 MB) partly"}
     return _common_out(args, flops / tot_batched / 1e9, "GFLOP/s", tot_batched / 3 * 1e3, "f32",
                        {"workload": "16^3x32, 12 spin-colour point sources per kappa in one batched CG launch, "
                                     "kappa in {0.130, 0.134, 0.1365}, complex64 inner / complex128 outer",
