@@ -674,6 +674,8 @@ def bench_pion(args):
     lat = W.Lattice(L, BC)
     for prec in ("f64", "f32", "f16"):
         lat.set_gauge(Ud, prec, 12)
+        if args.tune_file:
+            continue
         for nrhs in (1, 4):
             lat.autotune(prec, nrhs)
     res = {}
