@@ -176,6 +176,16 @@ void finish_launch(Launch& L) {
     const int per_slice = g.n / g.L[3];  // sites of one parity in a t-slice
     if (per_slice % L.sblk == 0) L.bt = per_slice / L.sblk * L.nslots;
   }
+  // the t-slices of an XCD's range, for ranges of q and q + 1 blocks
+  const int q = L.total_blocks >> 3;
+  for (int hi = 0; hi < 2; ++hi) {
+    const int cnt = q + hi, S = L.bt > 0 ? cnt / L.bt : 0;
+    L.tsS[hi] = S >= 2 && S * L.bt == cnt ? S : 0;
+    L.dts[hi] = make_fastdiv(L.tsS[hi]);
+  }
+  L.dpart = make_fastdiv(L.sblk * L.nrhs);
+  L.drhs = make_fastdiv(L.nrhs);
+  L.dslots = make_fastdiv(L.nslots);
 }
 
 Launch base_launch(int nrhs, const Tune& t, int parity) {
@@ -186,6 +196,11 @@ Launch base_launch(int nrhs, const Tune& t, int parity) {
   L.swz = t.swz;
   L.split = t.split;
   L.parity = parity;
+  // the divisors of a one-slot launch; finish_launch sets them for the final shape
+  L.dpart = make_fastdiv(L.sblk * L.nrhs);
+  L.drhs = make_fastdiv(L.nrhs);
+  L.dslots = make_fastdiv(1);
+  L.dts[0] = L.dts[1] = make_fastdiv(1);
   return L;
 }
 
@@ -482,6 +497,7 @@ wd_status wd_lattice_create(wd_lattice* out, const int32_t L[4], const int32_t b
   }
   lat->g.hx = L[0] / 2;
   lat->g.n = (int)(V / 2);
+  set_divisors(lat->g);
   *out = lat;
   return WD_OK;
 }

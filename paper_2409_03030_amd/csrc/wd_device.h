@@ -13,6 +13,8 @@
 
 #define WD_HD __host__ __device__ __forceinline__
 
+#include "wd_fastdiv.h"
+
 // Native vector type for non-temporal loads (the builtin takes clang vectors).
 typedef double wd_nt_d2 __attribute__((ext_vector_type(2)));
 typedef float wd_nt_f2 __attribute__((ext_vector_type(2)));
@@ -378,8 +380,16 @@ template <int P, int R> WD_HD size_t link_dir_bytes(size_t n) {
 struct Geom {
   int L[4];   // Lx, Ly, Lz, Lt
   int hx;     // Lx / 2
-  int n;      // sites per parity
+  int n;      // sites per parity (below 2^30)
+  FastDiv dhx, dy, dz;  // division by hx, Ly and Lz (set_divisors)
 };
+
+// Host: the divisors site_coord uses, from hx and L.
+inline void set_divisors(Geom& g) {
+  g.dhx = make_fastdiv(g.hx);
+  g.dy = make_fastdiv(g.L[1]);
+  g.dz = make_fastdiv(g.L[2]);
+}
 
 struct Coord {
   int c[4];
@@ -388,12 +398,12 @@ struct Coord {
 
 WD_HD Coord site_coord(const Geom& g, int parity, int s) {
   Coord k;
-  int xh = s % g.hx;
-  int rest = s / g.hx;
-  int y = rest % g.L[1];
-  int r2 = rest / g.L[1];
-  int z = r2 % g.L[2];
-  int t = r2 / g.L[2];
+  const int rest = fdiv(s, g.dhx);
+  const int xh = s - rest * g.hx;
+  const int r2 = fdiv(rest, g.dy);
+  const int y = rest - r2 * g.L[1];
+  const int t = fdiv(r2, g.dz);
+  const int z = r2 - t * g.L[2];
   k.c[0] = 2 * xh + ((parity + y + z + t) & 1);
   k.c[1] = y;
   k.c[2] = z;

@@ -28,16 +28,19 @@ struct Tile {
 // their uses (at 24^3x48 it cut the FP64 stencil's fetched bytes from 1.37 to
 // 1.10 times the algorithmic ones).  A range that is not whole slices keeps
 // the swz = 1 order.
-__device__ __forceinline__ int logical_block(int w, int nb, int swz, int bt) {
-  if (!swz) return w;
-  const int q = nb >> 3, rem = nb & 7;
+__device__ __forceinline__ int logical_block(int w, const Launch& L) {
+  if (!L.swz) return w;
+  const int q = L.total_blocks >> 3, rem = L.total_blocks & 7;
   const int x = w & 7;
   const int start = x * q + (x < rem ? x : rem);
   const int k = w >> 3;
-  if (swz == 2 && bt > 0) {
-    const int cnt = q + (x < rem ? 1 : 0);
-    const int S = cnt / bt;
-    if (S >= 2 && S * bt == cnt) return start + (k % S) * bt + k / S;
+  if (L.swz == 2) {
+    const int hi = x < rem ? 1 : 0;  // the range holds q + 1 blocks
+    const int S = L.tsS[hi];
+    if (S > 0) {
+      const int a = fdiv(k, L.dts[hi]);  // k / S
+      return start + (k - a * S) * L.bt + a;
+    }
   }
   return start + k;
 }
@@ -46,11 +49,11 @@ __device__ __forceinline__ int logical_block(int w, int nb, int swz, int bt) {
 // previous launch's reduction).
 __device__ __forceinline__ Tile make_tile(const Launch& L, int lead = 0) {
   Tile t;
-  const int b = logical_block((int)blockIdx.x - lead, L.total_blocks, L.swz, L.bt);
+  const int b = logical_block((int)blockIdx.x - lead, L);
   int sl = 0, lb;
   if (L.ilv) {
-    sl = b % L.nslots;
-    lb = b / L.nslots;
+    lb = fdiv(b, L.dslots);
+    sl = b - lb * L.nslots;
   } else {
 #pragma unroll 1
     for (int i = 1; i < L.nslots; ++i)
@@ -69,10 +72,11 @@ __device__ __forceinline__ Tile make_tile(const Launch& L, int lead = 0) {
   }
   const int per_part = L.sblk * L.nrhs;
   const int tid = (int)threadIdx.x;
-  t.part = tid / per_part;
+  t.part = fdiv(tid, L.dpart);
   const int loc = tid - t.part * per_part;
-  t.site = lb * L.sblk + loc / L.nrhs;
-  t.rhs = loc % L.nrhs;
+  const int sr = fdiv(loc, L.drhs);
+  t.site = lb * L.sblk + sr;
+  t.rhs = loc - sr * L.nrhs;
   t.valid = (t.part < (L.split > 0 ? L.split : 1)) && (t.site < S.g.n);
   return t;
 }

@@ -88,6 +88,10 @@ struct Launch {
                         // block count); logical block b is block b / nslots of slot b % nslots, so the
                         // groups' blocks for the same sites run next to each other (links read from the L2)
   int total_blocks;
+  int tsS[2];           // swz 2: t-slices in an XCD's range of q + 1 (index 1) or q (index 0) blocks, q =
+                        // total_blocks / 8, where that range is at least two whole slices; else 0
+  FastDiv dts[2];       // division by tsS[i]
+  FastDiv dpart, drhs, dslots;  // division by sblk * nrhs, nrhs and nslots (finish_launch)
   int* work_flag;       // timed launches: set to 1 by a block of a slot that does its work; else null
   double coef;          // epilogue coefficient when no RhsState is attached
   double coef2;         // second coefficient (staggered XPAY) when no RhsState is attached
