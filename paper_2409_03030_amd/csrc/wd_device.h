@@ -582,14 +582,6 @@ WD_HD void hop_dir(const Geom& g, const Coord& k, int parity, int s, int rhs, in
   int nb = neighbour_cb(g, k, MU, DIR);
   spinor<T> p;
   SpinorFmt<P>::load(in, ne, (size_t)nb * nrhs + rhs, p);
-  if (g5in) gamma5_inplace(p);
-  half_spinor<T> h, gh;
-  project<MU, DIR>(p, h);
-  bool crosses = DIR > 0 ? (k.c[MU] == g.L[MU] - 1) : (k.c[MU] == 0);
-  if (crosses && bc_sign < 0.f) {
-#pragma unroll
-    for (int j = 0; j < 6; ++j) h.c[j] = cneg(h.c[j]);
-  }
   su3<T> u;
   // forward: U_mu(x), rooted at the output site (parity `parity`);
   // backward: U_mu(x - mu), rooted at the neighbour (other parity).
@@ -598,6 +590,14 @@ WD_HD void hop_dir(const Geom& g, const Coord& k, int parity, int s, int rhs, in
   const char* lbase = gauge + (size_t)(lp * 4 + MU) * link_dir_bytes<P, R>(n);
   if constexpr (NT) LinkFmt<P, R>::load_nt(lbase, n, ls, u);
   else LinkFmt<P, R>::load(lbase, n, ls, u);
+  if (g5in) gamma5_inplace(p);
+  half_spinor<T> h, gh;
+  project<MU, DIR>(p, h);
+  bool crosses = DIR > 0 ? (k.c[MU] == g.L[MU] - 1) : (k.c[MU] == 0);
+  if (crosses && bc_sign < 0.f) {
+#pragma unroll
+    for (int j = 0; j < 6; ++j) h.c[j] = cneg(h.c[j]);
+  }
   if (DIR > 0) mul_link(u, h, gh);
   else mul_link_dag(u, h, gh);
   accumulate<MU, DIR>(acc, gh);
