@@ -399,6 +399,11 @@ def solve_workload(args, name, W, torch, tuned):
     cgr_name = stencil_kernel_name("f64", recon64, 2, split64, L)
     cgr_ms = lat.time_hop("f64", 1, n=200, mode=2)
     cgr_bytes = half * hop_bytes_per_site("f64", recon64, 2)
+    # the four stencil launches of one CG iteration (D_hat^dag D_hat with the
+    # fused epilogues), in order, back to back
+    seq_ms = lat.time_hop("f64", 1, n=50, mode=4)
+    seq_bytes = half * (2 * hop_bytes_per_site("f64", recon64, 0) + hop_bytes_per_site("f64", recon64, 1)
+                        + hop_bytes_per_site("f64", recon64, 2))
     roofline = {
         "bound": "hbm",
         "achieved": dom_bytes / (dom_ms * 1e-3) / 1e9,
@@ -422,6 +427,13 @@ def solve_workload(args, name, W, torch, tuned):
             "achieved": cgr_bytes / (cgr_ms * 1e-3) / 1e9,
             "frac": cgr_bytes / (cgr_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
             "traffic": lookup_traffic(cgr_name, lname)},
+        "cg_iteration_stencils": {
+            "what": "the 4 stencil launches of one CG iteration on D_hat^dag D_hat in order (plain H, aux - cH "
+                    "with |.|^2, plain H, CG residual update with |r|^2), repeated 50 times back to back "
+                    "(reductions' stage 1 included; stage 2 and the vector update not)",
+            "avg_ms": seq_ms, "bytes": seq_bytes,
+            "achieved": seq_bytes / (seq_ms * 1e-3) / 1e9,
+            "frac": seq_bytes / (seq_ms * 1e-3) / 1e9 / HBM_PEAK_GBS},
         "all_stencil_launches": {"achieved_gbs": roof["achieved_gbs"], "avg_launch_ms": roof["hop_ms_avg"],
                                  "launches": roof["hop_launches"], "gflops": roof["gflops"]},
     }

@@ -377,7 +377,12 @@ wd_status wd_solve_batch(int32_t nreq, const wd_solve_request* reqs, const wd_so
  * even-odd hop, V/2 output sites x nrhs, precision prec, the tuned launch
  * shape) with hipEvents on stream; *ms_per_launch gets the mean duration.
  * mode selects the epilogue: 0 = plain H, 1 = aux - c H with |.|^2 reduction,
- * 2 = the CG residual update r -= alpha (aux - c g5 H) with |r|^2 reduction.
+ * 2 = the CG residual update r -= alpha (aux - c g5 H) with |r|^2 reduction;
+ * or 4 = the four stencil launches of one CG iteration on D_hat^dag D_hat
+ * (App. C, "Definition of Dirac operators"), in order, repeated n times:
+ * t1 = H p, t2 = p - c H t1 (mode 1), t3 = H g5 t2, then mode 2 on t3 and t2;
+ * *ms_per_launch then gets the mean duration of the four together (the
+ * reductions' stage 1 included; their stage 2 and the vector update are not).
  * Operates on scratch data in the workspace (wd_apply_workspace_bytes(lat,
  * prec, nrhs) bytes, zeroed first).  Blocks the host. */
 wd_status wd_time_hop(wd_lattice lat, int32_t prec, int32_t nrhs, int32_t mode, int32_t n,

@@ -788,37 +788,63 @@ wd_status wd_solve_DdagD(wd_lattice lat, void* x, const void* b, int32_t nrhs, c
 // ---------------------------------------------------------------------------
 // measurement and tuning
 // ---------------------------------------------------------------------------
+// Mode of wd_time_hop: the four stencil launches of one CG iteration in order.
+constexpr int kTimeCgStencils = 4;
+
 static wd_status time_hop_shape(wd_lattice lat, int prec, int nrhs, int mode, int n, const Tune& t, char* ws,
                                 double* ms, hipStream_t st) {
   const size_t vb = vec_bytes(prec, (size_t)lat->g.n, nrhs);
   const int recon = lat->store[prec].recon;
-  Launch L = base_launch(nrhs, t, mode == HOP_PLAIN ? 1 : 0);
-  L.nslots = 1;
-  Slot& S = L.s[0];
-  fill_slot_geometry(S, lat, t.sblk, L.parity);
-  S.gauge = (const char*)lat->store[prec].ptr;
-  S.in = ws;
-  S.out = ws + 2 * vb;
-  S.aux = ws + 4 * vb;
-  S.r = ws + 6 * vb;
-  S.vstride = vb;
-  S.astride = vec_bytes(acc_prec(prec), (size_t)lat->g.n, nrhs);
   char* tail = ws + 8 * vb;
-  if (mode != HOP_PLAIN) {
-    L.fin = mode == HOP_XPAY ? FIN_ALPHA : FIN_CG;
-    L.mask = MASK_NONE;
-    S.st = (RhsState*)tail;
-    S.partial = (double*)(tail + align_up((size_t)nrhs * sizeof(RhsState)));
+  // Workspace blocks of both parities: 0 at ws, 1 at ws + 2 vb, 2 at ws + 4 vb,
+  // the residual at ws + 6 vb; solver states and partials after them.
+  auto make = [&](int m, int parity, const char* in, char* out, const char* aux, int g5in, int g5out) {
+    Launch L = base_launch(nrhs, t, parity);
+    L.nslots = 1;
+    L.g5in = g5in;
+    L.g5out = g5out;
+    Slot& S = L.s[0];
+    fill_slot_geometry(S, lat, t.sblk, L.parity);
+    S.gauge = (const char*)lat->store[prec].ptr;
+    S.in = in;
+    S.out = out;
+    S.aux = aux;
+    S.r = ws + 6 * vb;
+    S.vstride = vb;
+    S.astride = vec_bytes(acc_prec(prec), (size_t)lat->g.n, nrhs);
+    if (m != HOP_PLAIN) {
+      L.fin = m == HOP_XPAY ? FIN_ALPHA : FIN_CG;
+      L.mask = MASK_NONE;
+      S.st = (RhsState*)tail;
+      S.partial = (double*)(tail + align_up((size_t)nrhs * sizeof(RhsState)));
+    }
+    finish_launch(L);
+    return L;
+  };
+  std::vector<std::pair<Launch, int>> seq;
+  if (mode == kTimeCgStencils) {
+    // t1 = H_oe p; t2 = p - c H_eo t1 with |t2|^2; t3 = H_oe g5 t2;
+    // r -= alpha (t2 - c g5 H_eo t3) with |r|^2 (p, t2, r even; t1, t3 odd)
+    seq.push_back({make(HOP_PLAIN, 1, ws, ws + 2 * vb, nullptr, 0, 0), HOP_PLAIN});
+    seq.push_back({make(HOP_XPAY, 0, ws + 2 * vb, ws + 4 * vb, ws, 0, 0), HOP_XPAY});
+    seq.push_back({make(HOP_PLAIN, 1, ws + 4 * vb, ws + 2 * vb, nullptr, 1, 0), HOP_PLAIN});
+    seq.push_back({make(HOP_CGR, 0, ws + 2 * vb, ws + 4 * vb, ws + 4 * vb, 0, 1), HOP_CGR});
+  } else {
+    seq.push_back({make(mode, mode == HOP_PLAIN ? 1 : 0, ws, ws + 2 * vb, ws + 4 * vb, 0, 0), mode});
   }
-  finish_launch(L);
+  auto run = [&]() {
+    hipError_t e = hipSuccess;
+    for (size_t k = 0; k < seq.size() && e == hipSuccess; ++k) e = launch_hop(seq[k].first, prec, recon, seq[k].second, st);
+    return e;
+  };
   hipEvent_t e0, e1;
   WD_HIP(hipEventCreate(&e0));
   WD_HIP(hipEventCreate(&e1));
   wd_status res = WD_OK;
   hipError_t e = hipSuccess;
-  for (int i = 0; i < 3 && e == hipSuccess; ++i) e = launch_hop(L, prec, recon, mode, st);
+  for (int i = 0; i < 3 && e == hipSuccess; ++i) e = run();
   if (e == hipSuccess) e = hipEventRecord(e0, st);
-  for (int i = 0; i < n && e == hipSuccess; ++i) e = launch_hop(L, prec, recon, mode, st);
+  for (int i = 0; i < n && e == hipSuccess; ++i) e = run();
   if (e == hipSuccess) e = hipEventRecord(e1, st);
   if (e == hipSuccess) e = hipEventSynchronize(e1);
   float f = 0.f;
@@ -835,7 +861,8 @@ wd_status wd_time_hop(wd_lattice lat, int32_t prec, int32_t nrhs, int32_t mode, 
   wd_status s = check_lattice_for(lat, prec, WD_EO);
   if (s != WD_OK) return s;
   if (!ws || !ms_per_launch || n < 1) return fail(WD_EINVAL, "bad argument");
-  if (mode < HOP_PLAIN || mode > HOP_CGR) return fail(WD_EINVAL, "mode %d not timed (0, 1 or 2)", mode);
+  if (mode != HOP_PLAIN && mode != HOP_XPAY && mode != HOP_CGR && mode != kTimeCgStencils)
+    return fail(WD_EINVAL, "mode %d not timed (0, 1, 2 or 4)", mode);
   if (nrhs < 1 || nrhs > kBlock / 2) return fail(WD_EINVAL, "nrhs out of range");
   const size_t need = wd_apply_workspace_bytes(lat, prec, nrhs);
   if (ws_bytes < need) return fail(WD_EBUFSIZE, "workspace too small");

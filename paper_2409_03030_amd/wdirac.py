@@ -497,7 +497,8 @@ class Lattice:
 
     def time_hop(self, prec="f64", nrhs=1, n=50, mode=0, stream=None):
         """Mean duration (ms) of n back-to-back stencil launches; mode 0 plain,
-        1 with the aux - c H epilogue and reduction, 2 the fused CG residual update."""
+        1 with the aux - c H epilogue and reduction, 2 the fused CG residual update;
+        mode 4 the four stencil launches of one CG iteration in order (ms per four)."""
         nb = int(lib().wd_apply_workspace_bytes(self.handle, PREC[prec], nrhs))
         dev = next(iter(self.stores.values())).device
         ws = self._workspace(nb, dev, ("apply", PREC[prec], nrhs))

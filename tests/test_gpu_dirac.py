@@ -255,17 +255,19 @@ def test_launch_shapes_match_oracle(nrhs, split, sblk, swz):
 
 
 def test_time_hop_modes():
-    """The stencil timer runs every timed epilogue on scratch data and rejects others."""
+    """The stencil timer runs every timed epilogue, and the four stencils of a CG
+    iteration in order, on scratch data and rejects other modes."""
     W = _W()
     L = (8, 8, 8, 8)
     lat = _lattice(L, qcdgen.links_unit(L), [("f64", 12), ("f16", 12)])
     for prec in ("f64", "f16"):
-        for mode in (0, 1, 2):
+        for mode in (0, 1, 2, 4):
             ms = lat.time_hop(prec, 1, n=5, mode=mode)
             assert 0.0 < ms < 10.0
-    with pytest.raises(W.WDError) as e:
-        lat.time_hop("f64", 1, n=5, mode=3)
-    assert e.value.status == W.WD_EINVAL
+    for mode in (3, 5):
+        with pytest.raises(W.WDError) as e:
+            lat.time_hop("f64", 1, n=5, mode=mode)
+        assert e.value.status == W.WD_EINVAL
 
 
 def test_autotune_shapes_and_solve():
