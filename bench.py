@@ -42,7 +42,8 @@ def log(*a):
 # Sources that determine the stencil kernels' code; counter-derived traffic is
 # only reported while they are unchanged since the counters were taken.
 KERNEL_SOURCES = ["paper_2409_03030_amd/csrc/hop.hip", "paper_2409_03030_amd/csrc/wd_device.h",
-                  "paper_2409_03030_amd/csrc/wd_kcommon.h", "paper_2409_03030_amd/csrc/wd_launch.h"]
+                  "paper_2409_03030_amd/csrc/wd_kcommon.h", "paper_2409_03030_amd/csrc/wd_launch.h",
+                  "paper_2409_03030_amd/csrc/wd_fastdiv.h"]
 TRAFFIC_DB = os.path.join(ROOT, "profiles", "traffic.json")
 
 
