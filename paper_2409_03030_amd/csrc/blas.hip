@@ -9,6 +9,48 @@ namespace wd {
 
 template <int P> struct AccOfB { static constexpr int value = P == F16 ? F32 : P; };
 
+// The inner solution x (accumulation precision, FP64 or FP32) in the vector
+// update, read and written with the non-temporal hint: no stencil reads it,
+// so it need not take cache space from the vectors the stencils gather.
+template <typename TA>
+__device__ __forceinline__ void load_x_nt(const void* base, size_t ne, size_t e, spinor<TA>& s) {
+  if constexpr (sizeof(TA) == 8) {
+    const double2* v = (const double2*)base;
+#pragma unroll
+    for (int k = 0; k < 12; ++k) {
+      const wd_nt_d2 d = __builtin_nontemporal_load((const wd_nt_d2*)&v[k * ne + e]);
+      s.c[k] = {d.x, d.y};
+    }
+  } else {
+    const float4* v = (const float4*)base;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+      const wd_nt_f4 d = __builtin_nontemporal_load((const wd_nt_f4*)&v[k * ne + e]);
+      s.c[2 * k] = {d.x, d.y};
+      s.c[2 * k + 1] = {d.z, d.w};
+    }
+  }
+}
+
+template <typename TA>
+__device__ __forceinline__ void store_x_nt(void* base, size_t ne, size_t e, const spinor<TA>& s) {
+  if constexpr (sizeof(TA) == 8) {
+    double2* v = (double2*)base;
+#pragma unroll
+    for (int k = 0; k < 12; ++k) {
+      const wd_nt_d2 d = {s.c[k].re, s.c[k].im};
+      __builtin_nontemporal_store(d, (wd_nt_d2*)&v[k * ne + e]);
+    }
+  } else {
+    float4* v = (float4*)base;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+      const wd_nt_f4 d = {s.c[2 * k].re, s.c[2 * k].im, s.c[2 * k + 1].re, s.c[2 * k + 1].im};
+      __builtin_nontemporal_store(d, (wd_nt_f4*)&v[k * ne + e]);
+    }
+  }
+}
+
 // BLAS_INIT  : x_h = 0, x = 0, r = low(b), p = low(b);   ||b||^2 -> FIN_INIT
 // BLAS_CGUPD : x += alpha p (active rhs); p = r + beta p (running rhs); with
 //              prefin = FIN_CG every block first finishes the |r|^2 reduction
@@ -37,7 +79,7 @@ __global__ void __launch_bounds__(kBlock) blas_kernel(const Launch L) {
     spinor<TA> x, r;
     if (on) {  // issued before stage 2 so that both sets of loads are in flight together
       SpinorFmt<P>::load((const char*)S.out + pv, ne, e, p);
-      SpinorFmt<A>::load((const char*)S.x + pa, ne, e, x);
+      load_x_nt((const char*)S.x + pa, ne, e, x);
       SpinorFmt<A>::load((const char*)S.r + pa, ne, e, r);
     }
     __shared__ double s_beta[kBlock / 2];
@@ -59,7 +101,7 @@ __global__ void __launch_bounds__(kBlock) blas_kernel(const Launch L) {
         x.c[k].re += alpha * (TA)p.c[k].re;
         x.c[k].im += alpha * (TA)p.c[k].im;
       }
-      SpinorFmt<A>::store((char*)S.x + pa, ne, e, x);
+      store_x_nt((char*)S.x + pa, ne, e, x);
       if (state == ST_RUN) {
         const TA beta = (TA)beta_d;
         spinor<T> np;
