@@ -10,8 +10,9 @@ namespace wd {
 template <int P> struct AccOfB { static constexpr int value = P == F16 ? F32 : P; };
 
 // The inner solution x (accumulation precision, FP64 or FP32) in the vector
-// update, read and written with the non-temporal hint: no stencil reads it,
-// so it need not take cache space from the vectors the stencils gather.
+// update of a launch whose inner vectors exceed kStreamVecBytes, read and
+// written with the non-temporal hint: no stencil reads it, so it need not take
+// Infinity Cache space from the vectors the stencils gather.
 template <typename TA>
 __device__ __forceinline__ void load_x_nt(const void* base, size_t ne, size_t e, spinor<TA>& s) {
   if constexpr (sizeof(TA) == 8) {
@@ -56,7 +57,7 @@ __device__ __forceinline__ void store_x_nt(void* base, size_t ne, size_t e, cons
 //              prefin = FIN_CG every block first finishes the |r|^2 reduction
 // BLAS_RU_ACC: x_h += x, x = 0                            (held rhs)
 // BLAS_RU_FIN: r = low(r_h), p = r + beta p               (resumed rhs)
-template <int P, int MODE>
+template <int P, int MODE, bool XNT>
 __global__ void __launch_bounds__(kBlock) blas_kernel(const Launch L) {
   using T = typename RealOf<P>::T;
   constexpr int A = AccOfB<P>::value;
@@ -79,7 +80,8 @@ __global__ void __launch_bounds__(kBlock) blas_kernel(const Launch L) {
     spinor<TA> x, r;
     if (on) {  // issued before stage 2 so that both sets of loads are in flight together
       SpinorFmt<P>::load((const char*)S.out + pv, ne, e, p);
-      load_x_nt((const char*)S.x + pa, ne, e, x);
+      if constexpr (XNT) load_x_nt((const char*)S.x + pa, ne, e, x);
+      else SpinorFmt<A>::load((const char*)S.x + pa, ne, e, x);
       SpinorFmt<A>::load((const char*)S.r + pa, ne, e, r);
     }
     __shared__ double s_beta[kBlock / 2];
@@ -101,7 +103,8 @@ __global__ void __launch_bounds__(kBlock) blas_kernel(const Launch L) {
         x.c[k].re += alpha * (TA)p.c[k].re;
         x.c[k].im += alpha * (TA)p.c[k].im;
       }
-      store_x_nt((char*)S.x + pa, ne, e, x);
+      if constexpr (XNT) store_x_nt((char*)S.x + pa, ne, e, x);
+      else SpinorFmt<A>::store((char*)S.x + pa, ne, e, x);
       if (state == ST_RUN) {
         const TA beta = (TA)beta_d;
         spinor<T> np;
@@ -177,25 +180,37 @@ hipError_t launch_finalize(const Launch& L, hipStream_t stream) {
 }
 
 template <int P>
-static hipError_t blas_mode(const Launch& L, int mode, hipStream_t stream) {
+static hipError_t blas_mode(const Launch& L, int mode, bool xnt, hipStream_t stream) {
   dim3 grid((unsigned)L.total_blocks), block((unsigned)(L.sblk * L.nrhs));
   switch (mode) {
-    case BLAS_INIT: hipLaunchKernelGGL((blas_kernel<P, BLAS_INIT>), grid, block, 0, stream, L); break;
-    case BLAS_CGUPD: hipLaunchKernelGGL((blas_kernel<P, BLAS_CGUPD>), grid, block, 0, stream, L); break;
-    case BLAS_RU_ACC: hipLaunchKernelGGL((blas_kernel<P, BLAS_RU_ACC>), grid, block, 0, stream, L); break;
-    case BLAS_RU_FIN: hipLaunchKernelGGL((blas_kernel<P, BLAS_RU_FIN>), grid, block, 0, stream, L); break;
+    case BLAS_INIT: hipLaunchKernelGGL((blas_kernel<P, BLAS_INIT, false>), grid, block, 0, stream, L); break;
+    case BLAS_CGUPD:
+      if (xnt) hipLaunchKernelGGL((blas_kernel<P, BLAS_CGUPD, true>), grid, block, 0, stream, L);
+      else hipLaunchKernelGGL((blas_kernel<P, BLAS_CGUPD, false>), grid, block, 0, stream, L);
+      break;
+    case BLAS_RU_ACC: hipLaunchKernelGGL((blas_kernel<P, BLAS_RU_ACC, false>), grid, block, 0, stream, L); break;
+    case BLAS_RU_FIN: hipLaunchKernelGGL((blas_kernel<P, BLAS_RU_FIN, false>), grid, block, 0, stream, L); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
+}
+
+// Bytes of the inner CG's vectors in the launch's slots (p, t1, t2 at the inner
+// precision; x and r at the accumulation precision; both parities unless even-odd).
+static double inner_vector_bytes(const Launch& L) {
+  double b = 0.0;
+  for (int k = 0; k < L.nslots; ++k) b += 3.0 * (double)L.s[k].vstride + 2.0 * (double)L.s[k].astride;
+  return L.parity == 2 ? 2.0 * b : b;
 }
 
 hipError_t launch_blas(const Launch& L0, int prec, int mode, hipStream_t stream) {
   if (L0.total_blocks <= 0) return hipSuccess;
   Launch L = L0;
   L.split = 1;  // one thread per (site, rhs)
-  if (prec == F64) return blas_mode<F64>(L, mode, stream);
-  if (prec == F32) return blas_mode<F32>(L, mode, stream);
-  if (prec == F16) return blas_mode<F16>(L, mode, stream);
+  const bool xnt = mode == BLAS_CGUPD && inner_vector_bytes(L) > kStreamVecBytes;
+  if (prec == F64) return blas_mode<F64>(L, mode, xnt, stream);
+  if (prec == F32) return blas_mode<F32>(L, mode, xnt, stream);
+  if (prec == F16) return blas_mode<F16>(L, mode, xnt, stream);
   return hipErrorInvalidValue;
 }
 

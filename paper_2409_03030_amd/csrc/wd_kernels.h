@@ -56,6 +56,15 @@ inline double link_field_bytes(const Launch& L, int prec, int recon) {
 constexpr double kStreamLinkBytes = 192e6;
 constexpr double kStreamLaunchBytes = 768e6;
 
+// The CG vector update reads and writes the inner solution x, which no
+// stencil reads, with the non-temporal hint when the launch's inner vectors
+// exceed half the Infinity Cache.  (Measured, hinted against ordinary: the
+// 24^3x48 plain FP64 solve, 318 MB of vectors, 29.3 against 28.4 ms and the
+// FP32-inner one, 160 MB, 16.8 against 16.5 ms; 12 FP32 sources at 16^3x32,
+// 378 MB, 6-7 % faster batched solves; single 16^3x32 FP32-inner solves,
+// 32 MB, 2 % slower.)
+constexpr double kStreamVecBytes = 128e6;
+
 // CG vector kernel `mode` (BlasMode); prec is the precision of p (the
 // accumulation vectors x, r are F32 when prec is F16, else prec).
 hipError_t launch_blas(const Launch& L, int prec, int mode, hipStream_t stream);
