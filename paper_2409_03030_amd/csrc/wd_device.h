@@ -588,8 +588,13 @@ WD_HD void hop_dir(const Geom& g, const Coord& k, int parity, int s, int rhs, in
   const int lp = DIR > 0 ? parity : 1 - parity;
   const size_t ls = DIR > 0 ? (size_t)s : (size_t)nb;
   const char* lbase = gauge + (size_t)(lp * 4 + MU) * link_dir_bytes<P, R>(n);
-  if constexpr (NT) LinkFmt<P, R>::load_nt(lbase, n, ls, u);
-  else LinkFmt<P, R>::load(lbase, n, ls, u);
+  // 12-real links are loaded right after the spinor, so that both are in
+  // flight together; 18-real ones after the projection, since loading their
+  // 36 registers early cost waves per SIMD (FP64 with 2 parts: 2 -> 1).
+  if constexpr (R == 12) {
+    if constexpr (NT) LinkFmt<P, R>::load_nt(lbase, n, ls, u);
+    else LinkFmt<P, R>::load(lbase, n, ls, u);
+  }
   if (g5in) gamma5_inplace(p);
   half_spinor<T> h, gh;
   project<MU, DIR>(p, h);
@@ -597,6 +602,10 @@ WD_HD void hop_dir(const Geom& g, const Coord& k, int parity, int s, int rhs, in
   if (crosses && bc_sign < 0.f) {
 #pragma unroll
     for (int j = 0; j < 6; ++j) h.c[j] = cneg(h.c[j]);
+  }
+  if constexpr (R != 12) {
+    if constexpr (NT) LinkFmt<P, R>::load_nt(lbase, n, ls, u);
+    else LinkFmt<P, R>::load(lbase, n, ls, u);
   }
   if (DIR > 0) mul_link(u, h, gh);
   else mul_link_dag(u, h, gh);
