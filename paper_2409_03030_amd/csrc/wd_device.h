@@ -562,10 +562,10 @@ template <typename TO, typename TI> WD_HD void spinor_convert(spinor<TO>& o, con
 // block.  ne = n * nrhs is the chunk stride of the spinor block.
 //
 // Hop h (0..7) is direction mu = h / 2, forward for even h and backward for
-// odd h.  FP64 and FP32 run each hop in turn (hop_dir: spinor load,
-// projection, link load, product), relying on the waves in flight to hide
-// the latency.  FP16, whose stencil is bound by instruction issue rather than
-// memory, fetches the spinors and links of 4 hops first (all their loads in
+// odd h.  FP64 and FP32 run each hop in turn (hop_dir: spinor and link
+// loads, projection, product; 18-real links loaded after the projection),
+// relying on the waves in flight to hide the latency.  FP16, whose stencil is
+// bound by instruction issue rather than memory, fetches the spinors and links of 4 hops first (all their loads in
 // flight together, no branch between them) and then computes them.  Measured
 // on one box with the same launch shapes: the grouped form was 2-4 % faster
 // for FP16 (24^3x48, 32^3x64), but 4 % slower for the FP64 CG-residual
