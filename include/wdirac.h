@@ -399,9 +399,8 @@ wd_status wd_time_read(const void* buf, size_t bytes, int32_t n, void* out, size
 /* Autotune the stencil launch shape (sites per workgroup, block order: 0
  * plain, 1 each XCD a contiguous range of sites, 2 the same ranges visited
  * t-slice innermost; number of threads the 8 hops of a site are split over) for this
- * lattice, precision and nrhs by timing every candidate on stream (the mean
- * of the plain hop and of the CG-residual hop, which stand for the CG
- * iteration's two plain and two epilogue stencils).  Among
+ * lattice, precision and nrhs by timing every candidate on stream (the four
+ * stencil launches of one CG iteration in order, as wd_time_hop mode 4).  Among
  * the candidates whose workgroup count lets the CG fold its reductions (if
  * any do), of those within 3 % of the fastest, the one with the fewest
  * workgroups is chosen, XCD-aware order first (each reducing launch of the

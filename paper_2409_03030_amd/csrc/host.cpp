@@ -927,17 +927,9 @@ wd_status wd_autotune(wd_lattice lat, int32_t prec, int32_t nrhs, void* ws, size
         // the t-slice order exists only where the XCD ranges are whole t-slices
         if (swz == 2 && !tslice_order_applies(lat->g, sblk)) continue;
         WD_HIP(hipMemsetAsync(w + 2 * vb, 0, vb, st));
-        // the best of 3 timings of 20 launches: the shapes of a small lattice
-        // differ by a few percent, about the run-to-run spread of one timing.
-        // Timed: the plain hop and the CG-residual hop (the heaviest epilogue;
-        // the split shapes share it out over their parts), which stand for the
-        // CG iteration's two plain and two epilogue stencils.
-        double ms = 1e30, mc = 1e30;
-        for (int rep = 0; rep < 3; ++rep) {
-          double m1 = 0.0;
-          if ((s = time_hop_shape(lat, prec, nrhs, HOP_PLAIN, 20, t, w, &m1, st)) != WD_OK) return s;
-          ms = std::min(ms, m1);
-        }
+        // one plain hop for the output check below
+        double m1 = 0.0;
+        if ((s = time_hop_shape(lat, prec, nrhs, HOP_PLAIN, 1, t, w, &m1, st)) != WD_OK) return s;
         // within one split the per-site arithmetic does not depend on the tiling:
         // every shape must produce the same bytes
         got.resize(vb);
@@ -946,12 +938,16 @@ wd_status wd_autotune(wd_lattice lat, int32_t prec, int32_t nrhs, void* ws, size
         else if (memcmp(ref[split].data(), got.data(), vb) != 0)
           return fail(WD_EDEVICE, "tuning candidate sblk=%d swz=%d split=%d changed the stencil output", sblk, swz,
                       split);
+        // Timed: the four stencil launches of one CG iteration in order (two
+        // plain hops and the two epilogue stencils, as the solve runs them),
+        // the best of 3 timings of 5 iterations: the shapes of a small lattice
+        // differ by a few percent, about the run-to-run spread of one timing.
+        double mq = 1e30;
         for (int rep = 0; rep < 3; ++rep) {
-          double m1 = 0.0;
-          if ((s = time_hop_shape(lat, prec, nrhs, HOP_CGR, 20, t, w, &m1, st)) != WD_OK) return s;
-          mc = std::min(mc, m1);
+          if ((s = time_hop_shape(lat, prec, nrhs, kTimeCgStencils, 5, t, w, &m1, st)) != WD_OK) return s;
+          mq = std::min(mq, m1);
         }
-        timed.push_back({t, 0.5 * (ms + mc)});
+        timed.push_back({t, 0.25 * mq});  // per launch
       }
     }
   }
