@@ -377,7 +377,7 @@ constexpr double kEstShrink = 0.8;
 // 12 and 36 point sources: the early-leaning rule made the batched solves
 // 5-9 % slower through extra polls).
 int BlockPlanner::next(const RhsState* hs, size_t n, int inflight, const int* idx) {
-  double best = 1e30;
+  double best = 1e30, best_full = 1e30;
   bool any = false;
   nrun = 0;
   for (size_t j = 0; j < n; ++j) {
@@ -394,6 +394,7 @@ int BlockPlanner::next(const RhsState* hs, size_t n, int inflight, const int* id
     any = true;
     if (s.state == ST_HOLD) {  // its update runs at the end of the block in flight
       best = std::min(best, 1.0);
+      best_full = std::min(best_full, 1.0);
       continue;
     }
     const double rho = s.iter_res2 > 0.0 ? s.iter_res2 : s.rho;
@@ -406,7 +407,11 @@ int BlockPlanner::next(const RhsState* hs, size_t n, int inflight, const int* id
       rate = std::min(rate, std::log(rho / sn.rho) / (s.iters - sn.iters));
     if (lean && sn.iters0 >= 0 && s.iters > sn.iters0 && sn.rho0 > 0.0 && rho > 0.0)
       rate = std::min(rate, std::log(rho / sn.rho0) / (s.iters - sn.iters0));
-    if (rate < -1e-6) est = (lean ? kEstShrink : 1.0) * std::log(target / rho) / rate;
+    double est_full = est;
+    if (rate < -1e-6) {
+      est_full = std::log(target / rho) / rate;
+      est = (lean ? kEstShrink : 1.0) * est_full;
+    }
     if (sn.iters0 < 0 && rho > 0.0) {
       sn.iters0 = s.iters;
       sn.rho0 = rho;
@@ -415,9 +420,11 @@ int BlockPlanner::next(const RhsState* hs, size_t n, int inflight, const int* id
     sn.rho = rho;
     est = std::max(0.0, est);
     best = std::min(best, est);
+    best_full = std::min(best_full, std::max(0.0, est_full));
   }
   if (!any) return 0;
   left = best - inflight;  // iterations still needed after the blocks in flight
+  left_full = best_full - inflight;
   if (left < 0.5) return -1;  // the event falls in a block in flight: wait for it
   return round_block((int)std::ceil(left), kmax);
 }
@@ -666,12 +673,15 @@ wd_status run_batch(std::vector<EItem>& items, const wd_solve_params& p, RhsStat
         continue;
       }
       // the reliable-update sequence only in a block expected to reach the
-      // next event (a held rhs otherwise waits for the next block's)
-      if ((result = post(K, K + 0.5 >= plan.left)) != WD_OK) break;
+      // next event by the unshrunk extrapolation (a block sized to the
+      // early-leaning estimate usually ends short of it, and its sequence
+      // would run masked; a rhs that gets there early waits for the next
+      // block's sequence)
+      if ((result = post(K, K + 0.5 >= plan.left_full)) != WD_OK) break;
       iters_posted += K;
       if (fly.size() < 2 && K >= plan.kmax && (plan.nrun > 1 || plan.left >= 2.0 * K)) {
         // far from any event: keep a second block queued so the GPU never waits
-        if ((result = post(K, 2 * K + 0.5 >= plan.left)) != WD_OK) break;
+        if ((result = post(K, 2 * K + 0.5 >= plan.left_full)) != WD_OK) break;
         iters_posted += K;
       }
     }

@@ -215,6 +215,7 @@ struct BlockPlanner {
   std::vector<Snap> snap;
   int kmax = 32;
   double left = 0.0;  // iterations expected after the blocks in flight (last call of next)
+  double left_full = 0.0;  // the same without the early-leaning shrink (whether a block reaches the event)
   int nrun = 0;       // rhs not yet finished (last call of next)
   // > 0: size of the next block; -1: wait for the blocks in flight; 0: all done.
   // idx (optional) lists the state entries to consider; else entries 0..n-1.
