@@ -145,7 +145,8 @@ wd_status Engine::run_phase(const std::vector<EItem*>& list, const Phase& ph0) {
   while (i < list.size()) {
     // a launch: consecutive items with the same nrhs, the same link recon of
     // the store this phase reads (the kernel decodes every slot's links with
-    // one recon) and the same tuned launch shape, at most kMaxSlots.  The
+    // one recon), the same tuned launch shape and the same link-load
+    // decisions (item_streams_links), at most kMaxSlots.  The
     // shape fixes each slot's arithmetic (the hop split orders the sum over
     // the 8 hops, the block size the first stage of every reduction), so an
     // item computes the same bits whatever shares its launches.  Producer and
@@ -158,11 +159,21 @@ wd_status Engine::run_phase(const std::vector<EItem*>& list, const Phase& ph0) {
       return op_ == OP_STAG ? stag_tune_lookup(lat, ph.prec, recon, nrhs) : tune_lookup(lat, ph.prec, recon, nrhs);
     };
     const Tune t = lookup(lat0);
+    // the items' link-load decisions in every stencil mode at this precision
+    // (taken for each item on its own): equal within a launch
+    auto streams = [&](const wd_lattice_s* lat) {
+      int mask = 0;
+      for (int m = 0; m < (op_ == OP_STAG ? 5 : 4); ++m)
+        if (item_streams_links(lat->g.n, ph.parity, nrhs, ph.prec, recon, m, op_ == OP_STAG)) mask |= 1 << m;
+      return mask;
+    };
+    const int st0 = streams(lat0);
     size_t j = i + 1;
     while (j < list.size() && j - i < (size_t)kMaxSlots && list[j]->nrhs == nrhs &&
            list[j]->lat->store[ph.prec].recon == recon) {
       const Tune tj = lookup(list[j]->lat);
       if (tj.sblk != t.sblk || tj.split != t.split || tj.swz != t.swz) break;
+      if (streams(list[j]->lat) != st0) break;
       ++j;
     }
     Launch L = base_launch(nrhs, t, ph.parity);

@@ -299,15 +299,13 @@ static hipError_t launch_mode(const Launch& L, int mode, bool nt, hipStream_t st
   return hipErrorInvalidValue;
 }
 
-// Links take the non-temporal hint when the launch's link fields exceed
-// kStreamLinkBytes, or when an FP64 launch moves more than kStreamLaunchBytes
-// (FP64 and FP32; the FP16 stencil always loads them ordinarily).
+// Links take the non-temporal hint when an item's link field exceeds
+// kStreamLinkBytes, or when its FP64 launch alone would move more than
+// kStreamLaunchBytes (FP64 and FP32; the FP16 stencil always loads them
+// ordinarily).  Every slot of a launch has the same decision (the engine
+// groups only such items), so slot 0 decides.
 static bool stream_links(const Launch& L, int prec, int recon, int mode) {
-  if (prec == F16) return false;
-  long long sites = 0;
-  for (int k = 0; k < L.nslots; ++k) sites += (long long)L.s[k].g.n * (L.parity == 2 ? 2 : 1) * L.nrhs;
-  return link_field_bytes(L, prec, recon) > kStreamLinkBytes ||
-         (prec == F64 && hop_launch_bytes(prec, recon, mode, sites, L.nrhs) > kStreamLaunchBytes);
+  return item_streams_links(L.s[0].g.n, L.parity, L.nrhs, prec, recon, mode, false);
 }
 
 hipError_t launch_hop(const Launch& L, int prec, int recon, int mode, hipStream_t stream) {

@@ -185,10 +185,8 @@ hipError_t launch_stag(const Launch& L0, int prec, int recon, int mode, hipStrea
   const Launch& L = L0;
   if (L.split != 1 && L.split != 2 && L.split != 4) return hipErrorInvalidValue;
   if (L.split * L.sblk * L.nrhs > kBlock) return hipErrorInvalidValue;
-  long long sites = 0;
-  for (int k = 0; k < L.nslots; ++k) sites += (long long)L.s[k].g.n * (L.parity == 2 ? 2 : 1) * L.nrhs;
-  const bool nt = link_field_bytes(L, prec, recon) > kStreamLinkBytes ||
-                  (prec == F64 && stag_launch_bytes(prec, recon, mode, sites, L.nrhs) > kStreamLaunchBytes);
+  // every slot has the same decision (see item_streams_links)
+  const bool nt = item_streams_links(L.s[0].g.n, L.parity, L.nrhs, prec, recon, mode, true);
   if (prec == F64)
     return recon == 12 ? stag_mode<F64, 12>(L, mode, nt, stream) : stag_mode<F64, 18>(L, mode, nt, stream);
   if (prec == F32)

@@ -25,20 +25,6 @@ double hop_launch_bytes(int prec, int recon, int mode, long long sites, int nrhs
 // The same for the staggered stencil (StagMode).
 double stag_launch_bytes(int prec, int recon, int mode, long long sites, int nrhs);
 
-// Bytes of the link fields that a launch reads: each distinct gauge field
-// once (several slots may share one lattice), n sites per parity, 4 links per
-// site.
-inline double link_field_bytes(const Launch& L, int prec, int recon) {
-  const double link = (prec == F64 ? 16.0 : prec == F32 ? 8.0 : 4.0) * (recon == 12 ? 6 : 9);
-  double b = 0.0;
-  for (int k = 0; k < L.nslots; ++k) {
-    bool seen = false;
-    for (int j = 0; j < k; ++j) seen = seen || L.s[j].gauge == L.s[k].gauge;
-    if (!seen) b += (double)L.s[k].g.n * 8 * link;
-  }
-  return b;
-}
-
 // A stencil reads each link once.  Its links take the non-temporal hint when
 // they cannot stay in the 256 MB Infinity Cache until the next launch: when
 // the link field exceeds three quarters of it (kStreamLinkBytes), or, at FP64,
@@ -50,11 +36,26 @@ inline double link_field_bytes(const Launch& L, int prec, int recon) {
 // links of 127-191 MB (24^3x24) 11-15 % slower stencils; 12 FP64 fields at
 // 16^3x32 (launches up to 0.65 GB) 4 % slower propagators; FP64 links of
 // 255-382 MB (24^3x48) and FP32 links of 402 MB (32^3x64) 8-13 % and 10 %
-// faster stencils.  The launch-size condition keeps the FP64 launches of many
-// fields, such as the reliable updates of 36 fields at 16^3x32 at 1-1.8 GB,
-// on the hinted loads.)
+// faster stencils.  The launch-size condition keeps FP64 items that move more
+// than three times the Infinity Cache per launch on the hinted loads.)
 constexpr double kStreamLinkBytes = 192e6;
 constexpr double kStreamLaunchBytes = 768e6;
+
+// The decision is taken for each item (lattice and its nrhs fields) on its own,
+// as if it ran alone, and the solve engine puts only items with the same
+// decisions into one launch: the streamed and the ordinary kernels may round
+// differently (their code is scheduled apart), so an item's results would
+// otherwise depend on what shares its launches.  n sites per parity; parity 2
+// = both; stag: the staggered stencil's byte count.
+inline bool item_streams_links(long long n, int parity, int nrhs, int prec, int recon, int mode, bool stag) {
+  if (prec == F16) return false;
+  const double link = (prec == F64 ? 16.0 : 8.0) * (recon == 12 ? 6 : 9);
+  const long long sites = n * (parity == 2 ? 2 : 1) * nrhs;
+  if ((double)n * 8 * link > kStreamLinkBytes) return true;
+  if (prec != F64) return false;
+  const double b = stag ? stag_launch_bytes(prec, recon, mode, sites, nrhs) : hop_launch_bytes(prec, recon, mode, sites, nrhs);
+  return b > kStreamLaunchBytes;
+}
 
 // The CG vector update reads and writes the inner solution x, which no
 // stencil reads, with the non-temporal hint when the launch's inner vectors
