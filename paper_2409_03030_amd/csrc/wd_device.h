@@ -691,7 +691,8 @@ __device__ __forceinline__ void hop_finish16(HopBuf16& b, bool g5in, spinor<floa
 #pragma unroll
     for (int q = 0; q < 3; ++q) {
       ng[q] = -b.u[q];
-      sw[q] = -h2_swap(b.u[3 + q]);
+      const uint32_t v = __builtin_bit_cast(uint32_t, b.u[3 + q]);
+      sw[q] = h2_bits(((v >> 16) | (v << 16)) ^ 0x80008000u);  // (-x.im, -x.re)
     }
     // (a, b', d, c) row indices: e6 = conj(u1 u5 - u2 u4), e7 = conj(u2 u3 - u0 u5), e8 = conj(u0 u4 - u1 u3)
     constexpr int A_[3] = {1, 2, 0}, B_[3] = {2, 0, 1}, D_[3] = {5, 3, 4}, C_[3] = {4, 5, 3};
