@@ -63,7 +63,10 @@ inline bool item_streams_links(long long n, int parity, int nrhs, int prec, int 
 // 24^3x48 plain FP64 solve, 318 MB of vectors, 29.3 against 28.4 ms and the
 // FP32-inner one, 160 MB, 16.8 against 16.5 ms; 12 FP32 sources at 16^3x32,
 // 378 MB, 6-7 % faster batched solves; single 16^3x32 FP32-inner solves,
-// 32 MB, 2 % slower.)
+// 32 MB, 2 % slower.)  Unlike the links' hint this one is taken per launch:
+// it changes only the loads and stores of x, while each component's update is
+// the same single FMA in both kernels, so an item's results do not depend on
+// what shares its launches.
 constexpr double kStreamVecBytes = 128e6;
 
 // CG vector kernel `mode` (BlasMode); prec is the precision of p (the
