@@ -314,14 +314,14 @@ def oracle_residuals(U, L, kappa, cases):
         return list(ex.map(lambda xb: float(O.residual_DdagD(U, xb[0], xb[1], kappa, BC, True)), cases))
 
 
-# The link-load rule of the stencil launcher: FP64 and FP32 links take the
-# non-temporal hint (kernel hop_kernel_nt) when the launch's link field exceeds
-# 192 MB, or when an FP64 launch moves more than 768 MB.
+# The link-load rule of the stencil launcher: links take the non-temporal hint
+# (kernel hop_kernel_nt) when the item's link field exceeds 192 MB, or when an
+# FP64 launch moves more than 768 MB.
 def stencil_kernel_name(prec, recon, mode, split, L):
     half = L[0] * L[1] * L[2] * L[3] // 2
     link = {"f64": 16, "f32": 8, "f16": 4}[prec] * (9 if recon == 18 else 6)
     field = 2 * half * 4 * link
-    nt = prec != "f16" and (field > 192e6 or (prec == "f64" and half * hop_bytes_per_site(prec, recon, mode) > 768e6))
+    nt = field > 192e6 or (prec == "f64" and half * hop_bytes_per_site(prec, recon, mode) > 768e6)
     p = {"f64": 0, "f32": 1, "f16": 2}[prec]
     return f"void wd::hop_kernel{'_nt' if nt else ''}<{p}, {recon}, {mode}, {split}>"
 

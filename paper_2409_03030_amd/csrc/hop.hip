@@ -112,8 +112,8 @@ __device__ __forceinline__ double hop_epilogue_comps(const Launch& L, const Slot
   }
 }
 
-// NT: links read with the non-temporal hint (hop_kernel_nt, FP64 and FP32),
-// for launches whose links cannot stay in the Infinity Cache (stream_links).
+// NT: links read with the non-temporal hint (hop_kernel_nt), for launches
+// whose links cannot stay in the Infinity Cache (stream_links).
 template <int P, int R, int MODE, int D, bool NT>
 __device__ __forceinline__ void hop_body(const Launch& L) {
   using T = typename RealOf<P>::T;
@@ -262,11 +262,9 @@ template <int P, int R, int MODE, int D>
 static hipError_t launch_one(const Launch& L, bool nt, hipStream_t stream) {
   const int lead = L.prefin != FIN_NONE ? L.nslots : 0;  // finalize-only workgroups
   dim3 grid((unsigned)(L.total_blocks + lead)), block((unsigned)(D * L.sblk * L.nrhs));
-  if constexpr (P != F16) {
-    if (nt) {
-      hipLaunchKernelGGL((hop_kernel_nt<P, R, MODE, D>), grid, block, 0, stream, L);
-      return hipGetLastError();
-    }
+  if (nt) {
+    hipLaunchKernelGGL((hop_kernel_nt<P, R, MODE, D>), grid, block, 0, stream, L);
+    return hipGetLastError();
   }
   hipLaunchKernelGGL((hop_kernel<P, R, MODE, D>), grid, block, 0, stream, L);
   return hipGetLastError();
@@ -301,9 +299,8 @@ static hipError_t launch_mode(const Launch& L, int mode, bool nt, hipStream_t st
 
 // Links take the non-temporal hint when an item's link field exceeds
 // kStreamLinkBytes, or when its FP64 launch alone would move more than
-// kStreamLaunchBytes (FP64 and FP32; the FP16 stencil always loads them
-// ordinarily).  Every slot of a launch has the same decision (the engine
-// groups only such items), so slot 0 decides.
+// kStreamLaunchBytes.  Every slot of a launch has the same decision (the
+// engine groups only such items), so slot 0 decides.
 static bool stream_links(const Launch& L, int prec, int recon, int mode) {
   return item_streams_links(L.s[0].g.n, L.parity, L.nrhs, prec, recon, mode, false);
 }

@@ -19,6 +19,8 @@
 typedef double wd_nt_d2 __attribute__((ext_vector_type(2)));
 typedef float wd_nt_f2 __attribute__((ext_vector_type(2)));
 typedef float wd_nt_f4 __attribute__((ext_vector_type(4)));
+typedef unsigned int wd_nt_u2 __attribute__((ext_vector_type(2)));
+typedef unsigned int wd_nt_u4 __attribute__((ext_vector_type(4)));
 
 namespace wd {
 
@@ -632,7 +634,7 @@ struct HopBuf16 {
   bool flip;    // the hop crosses a boundary with sign -1
 };
 
-template <int R, int H>
+template <int R, int H, bool NT>
 __device__ __forceinline__ void hop_fetch16(const Geom& g, const Coord& k, int parity, int s, int rhs, int nrhs,
                                             const char* gauge, const void* in, const float bc[4], HopBuf16& b) {
   constexpr int MU = H >> 1;
@@ -656,7 +658,19 @@ __device__ __forceinline__ void hop_fetch16(const Geom& g, const Coord& k, int p
   const int lp = DIR > 0 ? parity : 1 - parity;
   const size_t ls = DIR > 0 ? (size_t)s : (size_t)nb;
   const char* lbase = gauge + (size_t)(lp * 4 + MU) * link_dir_bytes<F16, R>(n);
-  if constexpr (R == 12) {
+  // The non-temporal loads take integer vectors: loaded as float vectors and
+  // bit-cast to half pairs, some of a link's words were dropped by the compiled
+  // code (their registers reused while the load was in flight).
+  if constexpr (R == 12 && NT) {
+    const wd_nt_u4 d = __builtin_nontemporal_load((const wd_nt_u4*)lbase + ls);
+    const wd_nt_u2 f = __builtin_nontemporal_load((const wd_nt_u2*)(lbase + 16 * n) + ls);
+    b.u[0] = h2_bits(d.x);
+    b.u[1] = h2_bits(d.y);
+    b.u[2] = h2_bits(d.z);
+    b.u[3] = h2_bits(d.w);
+    b.u[4] = h2_bits(f.x);
+    b.u[5] = h2_bits(f.y);
+  } else if constexpr (R == 12) {
     const uint4 d = ((const uint4*)lbase)[ls];
     const uint2 f = ((const uint2*)(lbase + 16 * n))[ls];
     b.u[0] = h2_bits(d.x);
@@ -665,6 +679,10 @@ __device__ __forceinline__ void hop_fetch16(const Geom& g, const Coord& k, int p
     b.u[3] = h2_bits(d.w);
     b.u[4] = h2_bits(f.x);
     b.u[5] = h2_bits(f.y);
+  } else if constexpr (NT) {
+    const uint32_t* lv = (const uint32_t*)lbase;
+#pragma unroll
+    for (int q = 0; q < 9; ++q) b.u[q] = h2_bits(__builtin_nontemporal_load(&lv[q * n + ls]));
   } else {
     const uint32_t* lv = (const uint32_t*)lbase;
 #pragma unroll
@@ -735,11 +753,11 @@ __device__ __forceinline__ void hop_finish16(HopBuf16& b, bool g5in, spinor<floa
   accumulate_scaled<MU, DIR>(acc, gh, b.flip ? -b.w : b.w);
 }
 
-template <int R, int H0, int... J>
+template <int R, int H0, bool NT, int... J>
 __device__ __forceinline__ void hop_fetch_group16(std::integer_sequence<int, J...>, const Geom& g, const Coord& k,
                                                   int parity, int s, int rhs, int nrhs, const char* gauge,
                                                   const void* in, const float bc[4], HopBuf16* b) {
-  (hop_fetch16<R, H0 + J>(g, k, parity, s, rhs, nrhs, gauge, in, bc, b[J]), ...);
+  (hop_fetch16<R, H0 + J, NT>(g, k, parity, s, rhs, nrhs, gauge, in, bc, b[J]), ...);
 }
 
 template <int R, int H0, int... J>
@@ -760,7 +778,7 @@ WD_HD void hop_range(const Geom& g, const Coord& k, int parity, int s, int rhs, 
   } else if constexpr (NH > 0) {
     constexpr int M = NH < 4 ? NH : 4;
     HopBuf16 b[M];
-    hop_fetch_group16<R, H0>(std::make_integer_sequence<int, M>{}, g, k, parity, s, rhs, nrhs, gauge, in, bc, b);
+    hop_fetch_group16<R, H0, NT>(std::make_integer_sequence<int, M>{}, g, k, parity, s, rhs, nrhs, gauge, in, bc, b);
     hop_finish_group16<R, H0>(std::make_integer_sequence<int, M>{}, b, g5in, acc);
     hop_range<P, R, H0 + M, NH - M, NT>(g, k, parity, s, rhs, nrhs, gauge, in, bc, g5in, acc);
   }

@@ -36,8 +36,10 @@ double stag_launch_bytes(int prec, int recon, int mode, long long sites, int nrh
 // links of 127-191 MB (24^3x24) 11-15 % slower stencils; 12 FP64 fields at
 // 16^3x32 (launches up to 0.65 GB) 4 % slower propagators; FP64 links of
 // 255-382 MB (24^3x48) and FP32 links of 402 MB (32^3x64) 8-13 % and 10 %
-// faster stencils.  The launch-size condition keeps FP64 items that move more
-// than three times the Infinity Cache per launch on the hinted loads.)
+// faster stencils; FP16 links of 201 and 302 MB (32^3x64, recon 12 and 18)
+// the four stencils of a CG iteration 8 % and 12 % faster.  The launch-size
+// condition keeps FP64 items that move more than three times the Infinity
+// Cache per launch on the hinted loads.)
 constexpr double kStreamLinkBytes = 192e6;
 constexpr double kStreamLaunchBytes = 768e6;
 
@@ -48,8 +50,7 @@ constexpr double kStreamLaunchBytes = 768e6;
 // otherwise depend on what shares its launches.  n sites per parity; parity 2
 // = both; stag: the staggered stencil's byte count.
 inline bool item_streams_links(long long n, int parity, int nrhs, int prec, int recon, int mode, bool stag) {
-  if (prec == F16) return false;
-  const double link = (prec == F64 ? 16.0 : 8.0) * (recon == 12 ? 6 : 9);
+  const double link = (prec == F64 ? 16.0 : prec == F32 ? 8.0 : 4.0) * (recon == 12 ? 6 : 9);
   const long long sites = n * (parity == 2 ? 2 : 1) * nrhs;
   if ((double)n * 8 * link > kStreamLinkBytes) return true;
   if (prec != F64) return false;

@@ -6,7 +6,8 @@
   reliable updates at 1e-2), each in the launch shapes the autotuner picks
   and the plain FP64 CG also with 4 threads per site (the non-temporal
   recon-12 stencil), each to the oracle's FP64 true residual of 1e-10.
-* 32^3x64 with FP32 recon-12 links (402 MB, streamed): D at sampled sites.
+* 32^3x64 with FP32 recon-12 (402 MB) and FP16 recon-12 and recon-18 links (201 and
+  302 MB), all streamed: D at sampled sites.
 * 16^3x32, links exp(0.3 i H): 12 spin-colour point sources per kappa in
   {0.130, 0.134, 0.1365} in one batched solve (FP32 inner), and all 36 in
   one solve with per-rhs kappa; every column to the oracle's 1e-10.
@@ -128,28 +129,36 @@ def test_cfg3_solve(cfg3, inner):
         assert sts[0]["reliable_updates"] >= 2
 
 
-def test_streamed_fp32_recon12_sampled_sites():
-    """32^3x64 with FP32 recon-12 links (402 MB, beyond three quarters of the
-    Infinity Cache): the streamed FP32 recon-12 stencil at 128 sampled sites,
-    corners included, against the oracle's site-wise D."""
+@pytest.fixture(scope="module")
+def big():
     L = (32, 32, 32, 64)
     U = qcdgen.links_exp(L, 0.4, qcdgen.rng(qcdgen.CONFIG_SEED_BASE + 2))
     b = qcdgen.gaussian_spinor(L, qcdgen.rng(qcdgen.CONFIG_SEED_BASE + 103))
-    W = _W()
-    lat = W.Lattice(L, BC)
-    Ud = _dev(U)
-    assert lat.gauge_bytes("f32", 12) > 192e6
-    lat.set_gauge(Ud, "f32", 12)
-    del Ud
-    y = _host(lat.apply_D(_dev(b), 0.137, precond=W.FULL, prec="f32"))
     g = qcdgen.rng(11)
     sites = [(0, 0, 0, 0), (L[0] - 1, L[1] - 1, L[2] - 1, L[3] - 1), (0, L[1] - 1, 0, L[3] - 1),
              (L[0] - 1, 0, L[2] - 1, 0)]
     sites += [tuple(int(g.integers(0, L[m])) for m in range(4)) for _ in range(124)]
     ref = O.apply_D_sites(U, b, 0.137, BC, sites)
+    return L, U, b, sites, ref
+
+
+@pytest.mark.parametrize("prec,recon,tol", [("f32", 12, 1e-5), ("f16", 12, 3e-3), ("f16", 18, 3e-3)])
+def test_streamed_links_sampled_sites(big, prec, recon, tol):
+    """32^3x64 with link fields beyond three quarters of the Infinity Cache
+    (FP32 recon-12 402 MB, FP16 recon-12 201 MB, FP16 recon-18 302 MB): the
+    streamed stencils at 128 sampled sites, corners included, against the
+    oracle's site-wise D."""
+    L, U, b, sites, ref = big
+    W = _W()
+    lat = W.Lattice(L, BC)
+    Ud = _dev(U)
+    assert lat.gauge_bytes(prec, recon) > 192e6
+    lat.set_gauge(Ud, prec, recon)
+    del Ud
+    y = _host(lat.apply_D(_dev(b), 0.137, precond=W.FULL, prec=prec))
     got = np.stack([y[t, z, yy, x] for (x, yy, z, t) in sites])
     err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
-    assert err < 1e-5, err
+    assert err < tol, err
     lat.close()
 
 

@@ -1,0 +1,81 @@
+"""Properties of the compiled stencil code, checked on the host.
+
+The stencil is compiled twice per shape: with ordinary link loads
+(`hop_kernel`) and with non-temporal ones (`hop_kernel_nt`, for link fields
+that cannot stay in the Infinity Cache).  For FP16 the hinted kernels must be
+the ordinary ones with only the hint bits added: then both give the same
+bits, and what the parity tests establish for one holds for the other.  (A
+version that loaded the hinted FP16 links as float vectors broke this: the
+compiled code reused the registers of some link words while their loads were
+still in flight.)  The check compiles the stencil source to gfx950 assembly
+with the library's own flags and compares the two kernels of every FP16
+shape instruction by instruction, branch label numbers aside.
+"""
+
+import os
+import re
+import subprocess
+
+import pytest
+
+from paper_2409_03030_amd import build as B
+
+
+def _hipcc():
+    try:
+        return B._hipcc()
+    except RuntimeError:
+        return None
+
+
+@pytest.fixture(scope="module")
+def hop_asm(tmp_path_factory):
+    hipcc = _hipcc()
+    if hipcc is None:
+        pytest.skip("hipcc not found")
+    out = str(tmp_path_factory.mktemp("asm") / "hop.s")
+    flags = [f for f in B.HIPFLAGS if not f.startswith("-W")]
+    cmd = [hipcc, *flags, "--cuda-device-only", "-x", "hip", "-S", os.path.join(B.CSRC, "hop.hip"), "-o", out]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr[-2000:]
+    with open(out) as f:
+        return f.read().split("\n")
+
+
+def _kernels(lines):
+    """Instruction lists of every function, branch label numbers removed."""
+    funcs, cur, buf = {}, None, []
+    for line in lines:
+        m = re.match(r"^(_Z\S+):\s*(;.*)?$", line)
+        if m:
+            cur, buf = m.group(1), []
+            continue
+        if cur and line.startswith(".Lfunc_end"):
+            funcs[cur] = buf
+            cur = None
+            continue
+        s = line.strip()
+        if cur and s and not s.startswith(";") and not s.startswith("."):
+            buf.append(re.sub(r"\.LBB\d+_", ".LBB_", s))
+    return funcs
+
+
+def _name(nt, prec, recon, mode, split):
+    base = "13hop_kernel_nt" if nt else "10hop_kernel"
+    return f"_ZN2wd{base}ILi{prec}ELi{recon}ELi{mode}ELi{split}EEEvNS_6LaunchE"
+
+
+def test_fp16_hinted_kernels_equal_ordinary_ones(hop_asm):
+    funcs = _kernels(hop_asm)
+    checked = 0
+    for recon in (12, 18):
+        for mode in (0, 1, 2):
+            for split in (1, 2, 4, 8):
+                plain = funcs[_name(False, 2, recon, mode, split)]
+                hinted = funcs[_name(True, 2, recon, mode, split)]
+                nt_loads = sum(1 for s in hinted if s.startswith("global_load") and s.endswith(" nt"))
+                assert nt_loads >= 8, (recon, mode, split, nt_loads)
+                stripped = [s[:-3] if s.endswith(" nt") else s for s in hinted]
+                assert stripped == plain, (recon, mode, split)
+                checked += 1
+    assert checked == 24
