@@ -10,6 +10,11 @@ compiled code reused the registers of some link words while their loads were
 still in flight.)  The check compiles the stencil source to gfx950 assembly
 with the library's own flags and compares the two kernels of every FP16
 shape instruction by instruction, branch label numbers aside.
+
+The CG vector update likewise has a variant that reads and writes the inner
+solution with the hint, chosen per launch from the size of all its items'
+vectors; that is sound only while the two variants do the same floating-point
+arithmetic, which the second check compares.
 """
 
 import os
@@ -28,18 +33,27 @@ def _hipcc():
         return None
 
 
-@pytest.fixture(scope="module")
-def hop_asm(tmp_path_factory):
+def _asm(tmp_path_factory, src):
     hipcc = _hipcc()
     if hipcc is None:
         pytest.skip("hipcc not found")
-    out = str(tmp_path_factory.mktemp("asm") / "hop.s")
+    out = str(tmp_path_factory.mktemp("asm") / (src + ".s"))
     flags = [f for f in B.HIPFLAGS if not f.startswith("-W")]
-    cmd = [hipcc, *flags, "--cuda-device-only", "-x", "hip", "-S", os.path.join(B.CSRC, "hop.hip"), "-o", out]
+    cmd = [hipcc, *flags, "--cuda-device-only", "-x", "hip", "-S", os.path.join(B.CSRC, src), "-o", out]
     r = subprocess.run(cmd, capture_output=True, text=True)
     assert r.returncode == 0, r.stderr[-2000:]
     with open(out) as f:
         return f.read().split("\n")
+
+
+@pytest.fixture(scope="module")
+def hop_asm(tmp_path_factory):
+    return _asm(tmp_path_factory, "hop.hip")
+
+
+@pytest.fixture(scope="module")
+def blas_asm(tmp_path_factory):
+    return _asm(tmp_path_factory, "blas.hip")
 
 
 def _kernels(lines):
@@ -79,3 +93,19 @@ def test_fp16_hinted_kernels_equal_ordinary_ones(hop_asm):
                 assert stripped == plain, (recon, mode, split)
                 checked += 1
     assert checked == 24
+
+
+_FP_OPS = re.compile(r"^v_(pk_)?(fma|fmac|mul|add|sub|subrev|cvt|div|rcp|sqrt|max|min)\S*_f(16|32|64)")
+
+
+def test_cg_update_hint_keeps_its_arithmetic(blas_asm):
+    """blas_kernel<P, BLAS_CGUPD, XNT>: the same floating-point instructions
+    (as a multiset) with and without the hint on x, at each precision."""
+    funcs = _kernels(blas_asm)
+    for prec in (0, 1, 2):
+        ops = []
+        for xnt in (0, 1):
+            body = funcs[f"_ZN2wd11blas_kernelILi{prec}ELi1ELb{xnt}EEEvNS_6LaunchE"]
+            ops.append(sorted(s.split()[0] for s in body if _FP_OPS.match(s)))
+        assert len(ops[0]) > 20, prec
+        assert ops[0] == ops[1], prec
