@@ -15,6 +15,9 @@ The CG vector update likewise has a variant that reads and writes the inner
 solution with the hint, chosen per launch from the size of all its items'
 vectors; that is sound only while the two variants do the same floating-point
 arithmetic, which the second check compares.
+
+The third check reads every stencil and vector kernel for the failure itself:
+a register written while a global load that fills it is still outstanding.
 """
 
 import os
@@ -109,3 +112,53 @@ def test_cg_update_hint_keeps_its_arithmetic(blas_asm):
             ops.append(sorted(s.split()[0] for s in body if _FP_OPS.match(s)))
         assert len(ops[0]) > 20, prec
         assert ops[0] == ops[1], prec
+
+
+def _outstanding_overwrites(body):
+    """Instructions that write a register while a global load into it is
+    still outstanding: no s_waitcnt vmcnt since the load has retired it
+    (vector loads and stores retire in issue order and both count in vmcnt).
+    A straight-line reading of the listing: across branches it can only err
+    towards reporting more."""
+    pend, bad = [], []
+    for s in body:
+        if s.startswith("s_waitcnt"):
+            m = re.search(r"vmcnt\((\d+)\)", s)
+            if m:
+                k = int(m.group(1))
+                pend = pend[len(pend) - k:] if 0 < k < len(pend) else ([] if k == 0 else pend)
+            continue
+        parts = s.replace(",", " ").split()
+        op = parts[0]
+        if op.startswith("s_") or len(parts) < 2:
+            continue
+        is_store = op.startswith(("global_store", "buffer_store", "global_atomic"))
+        dst = set()
+        if not is_store:
+            m = re.match(r"v\[(\d+):(\d+)\]$", parts[1])
+            if m:
+                dst = set(range(int(m.group(1)), int(m.group(2)) + 1))
+            else:
+                m = re.match(r"v(\d+)$", parts[1])
+                dst = {int(m.group(1))} if m else set()
+        if any(dst & r for r, _ in pend):
+            bad.append(s)
+        if op.startswith(("global_load", "buffer_load")):
+            pend.append((dst, s))
+        elif is_store:
+            pend.append((set(), s))
+    return bad
+
+
+def test_no_register_rewritten_under_an_outstanding_load(hop_asm, blas_asm):
+    """Every Wilson stencil and CG vector kernel: no instruction writes a
+    register that an outstanding global load is still to fill (the failure
+    of the float-vector FP16 link loads)."""
+    checked = 0
+    for asm in (hop_asm, blas_asm):
+        for name, body in _kernels(asm).items():
+            if "hop_kernel" not in name and "blas_kernel" not in name:
+                continue
+            assert _outstanding_overwrites(body) == [], name
+            checked += 1
+    assert checked >= 144
